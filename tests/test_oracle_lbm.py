@@ -1,0 +1,399 @@
+"""Pins of the FP64 lattice Boltzmann oracle (oracle/lbm_oracle.c) against what the
+paper and the mathematics fix: closed forms, exact identities between the paper's
+equations, invariants, textbook special cases and the analysis oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import lbm
+from oracle import thermo as th
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+EX, EY = lbm.EX.astype(float), lbm.EY.astype(float)
+CS2 = 1.0 / 3.0
+
+
+def cs_params(t=0.8, **kw):
+    Tc, _ = th.critical_cs()
+    kw.setdefault("nx", 3)
+    kw.setdefault("ny", 3)
+    return lbm.Params(T=t * Tc, **kw)
+
+
+def general_form(B, C):
+    """Eq. (12): F_a = w [B.e/c_s^2 + C:(ee - c_s^2 I)/(2 c_s^4)] (delta_t = 1)."""
+    W = lbm.feq(1.0, 0.0, 0.0)
+    out = np.zeros(9)
+    for a in range(9):
+        e = np.array([EX[a], EY[a]])
+        Q = np.outer(e, e) - CS2 * np.eye(2)
+        out[a] = W[a] * (B @ e / CS2 + np.sum(C * Q) / (2 * CS2 * CS2))
+    return out
+
+
+def moments9(g):
+    m0 = g.sum()
+    m1 = np.array([(g * EX).sum(), (g * EY).sum()])
+    m2 = np.array([[(g * EX * EX).sum(), (g * EX * EY).sum()],
+                   [(g * EY * EX).sum(), (g * EY * EY).sum()]])
+    return m0, m1, m2
+
+
+# ---------------------------------------------------------------- Eq. (2)
+
+def test_equilibrium_weights_are_the_papers():
+    g = GOLD["d2q9_weights"]
+    w = lbm.feq(1.0, 0.0, 0.0)
+    assert np.allclose(w, [g["w0"]] + [g["w1_4"]] * 4 + [g["w5_8"]] * 4, rtol=0, atol=1e-16)
+
+
+def test_equilibrium_moments_closed_form():
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        rho = rng.uniform(0.01, 2.0)
+        u = rng.uniform(-0.2, 0.2, 2)
+        m0, m1, m2 = moments9(lbm.feq(rho, *u))
+        assert abs(m0 - rho) < 1e-15 * 9
+        assert np.allclose(m1, rho * u, rtol=0, atol=1e-15)
+        assert np.allclose(m2, rho * CS2 * np.eye(2) + rho * np.outer(u, u), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- Eq. (3)-(4)
+
+def _force_1d(N, m, G=-1.0, axis=0, amp=0.05):
+    k = 2 * np.pi * m / N
+    s = np.arange(N, dtype=float)
+    prof = 0.3 + amp * np.sin(k * s)
+    d1 = amp * k * np.cos(k * s)
+    d3 = -amp * k ** 3 * np.cos(k * s)
+    if axis == 0:
+        psi = np.broadcast_to(prof, (3, N)).copy()
+        p = lbm.Params(nx=N, ny=3, G=G)
+    else:
+        psi = np.broadcast_to(prof[:, None], (N, 3)).copy()
+        p = lbm.Params(nx=3, ny=N, G=G)
+    Fx, Fy = lbm.interaction_force(p, psi)
+    F_along, F_across = (Fx[0], Fy[0]) if axis == 0 else (Fy[:, 0], Fx[:, 0])
+    return F_along, F_across, prof, d1, d3
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_force_taylor_expansion(axis):
+    # Eq. (4): F = -G [psi grad psi + (1/6) psi grad lap psi] + O(k^5) for w(1)=1/3,
+    # w(2)=1/12 (exact expansion of Eq. 3; the second coefficient is 1/6 for these weights)
+    G = -1.0
+    errs0, errs1 = [], []
+    for N in (64, 128, 256):
+        F, Fc, prof, d1, d3 = _force_1d(N, 2, G, axis)
+        assert np.abs(Fc).max() < 1e-17           # no force across the wave (rounding only)
+        lead = -G * prof * d1
+        errs0.append(np.abs(F - lead).max())
+        errs1.append(np.abs(F - lead + G * prof * d3 / 6.0).max())
+    # leading-order residual falls like k^3, the corrected one like k^5
+    assert 7.0 < errs0[0] / errs0[1] < 9.0 and 7.0 < errs0[1] / errs0[2] < 9.0
+    assert 28.0 < errs1[0] / errs1[1] < 36.0
+
+
+def test_force_sums_to_zero_periodic():
+    rng = np.random.default_rng(2)
+    psi = rng.uniform(0.1, 0.6, (17, 23))
+    Fx, Fy = lbm.interaction_force(lbm.Params(nx=23, ny=17), psi)
+    assert abs(Fx.sum()) < 1e-14 * psi.size and abs(Fy.sum()) < 1e-14 * psi.size
+    # uniform psi gives exactly zero force
+    Fx, Fy = lbm.interaction_force(lbm.Params(nx=23, ny=17), np.full((17, 23), 0.37))
+    assert np.all(Fx == 0.0) and np.all(Fy == 0.0)
+
+
+def test_force_stencil_weights_on_delta():
+    # a single raised psi at one node: the force on each neighbour points towards it
+    # with magnitude G psi0 w(|e|^2) dpsi, w(1) = 1/3, w(2) = 1/12 (Eq. 3)
+    G, p0, d = -1.0, 0.2, 0.05
+    psi = np.full((9, 9), p0)
+    psi[4, 4] += d
+    Fx, Fy = lbm.interaction_force(lbm.Params(nx=9, ny=9, G=G), psi)
+    w = GOLD["interaction_weights"]
+    for a in range(1, 9):
+        x, y = 4 - lbm.EX[a], 4 - lbm.EY[a]          # the neighbour that sees node (4,4) at +e_a
+        wa = w["w1"] if a <= 4 else w["w2"]
+        assert abs(Fx[y, x] - (-G * p0 * wa * d * EX[a])) < 1e-16
+        assert abs(Fy[y, x] - (-G * p0 * wa * d * EY[a])) < 1e-16
+
+
+# ---------------------------------------------------------------- Eq. (8), (23)
+
+def test_psi_eq8_and_cs_eos():
+    p = cs_params(0.8)
+    for rho in (0.01, 0.1, 0.3):
+        eta = rho
+        pe = rho * p.T * (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3 - rho ** 2
+        assert abs(lbm.p_eos(p, rho) - pe) < 1e-15
+        psi = lbm.psi(p, rho)
+        # Eq. (5) with Eq. (8): rho c_s^2 + G psi^2 / 2 = p_EOS
+        assert abs(rho / 3 + p.G * psi * psi / 2 - pe) < 1e-15
+    # outside the EOS range the oracle refuses (argument of the square root <= 0)
+    assert lbm.psi(p, 0.9) is None
+
+
+# ---------------------------------------------------------------- Eqs. (9)-(16), (31), Table I
+
+def _random_node(rng):
+    return (rng.uniform(0.02, 0.45), rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05),
+            rng.uniform(-0.01, 0.01), rng.uniform(-0.01, 0.01), rng.uniform(0.02, 0.3))
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.3])
+def test_shan_chen_is_general_form_eq15(tau):
+    rng = np.random.default_rng(3)
+    p = cs_params(scheme=lbm.SCHEME_SC, tau=tau, nx=3, ny=3)
+    for _ in range(30):
+        rho, ux, uy, Fx, Fy, s2 = _random_node(rng)
+        ueq, Fa = lbm.forcing(p, rho, ux, uy, Fx, Fy, s2)
+        assert np.all(Fa == 0.0)
+        assert ueq == (ux + tau * Fx / rho, uy + tau * Fy / rho)          # Eq. (10)
+        # Eq. (14): f_eq(rho, u_eq) - f_eq(rho, u) = tau * Eq. (15) with v_SC = u + tau F/(2 rho)
+        F = np.array([Fx, Fy])
+        v = np.array([ux, uy]) + tau * F / (2 * rho)
+        ref = general_form(F, np.outer(v, F) + np.outer(F, v))
+        got = (lbm.feq(rho, *ueq) - lbm.feq(rho, ux, uy)) / tau
+        assert np.allclose(got, ref, rtol=0, atol=1e-15)
+
+
+def test_edm_is_general_form_eq16():
+    rng = np.random.default_rng(4)
+    p = cs_params(scheme=lbm.SCHEME_EDM, tau=0.7, nx=3, ny=3)
+    for _ in range(30):
+        rho, ux, uy, Fx, Fy, s2 = _random_node(rng)
+        ueq, Fa = lbm.forcing(p, rho, ux, uy, Fx, Fy, s2)
+        assert ueq == (ux, uy)
+        F = np.array([Fx, Fy])
+        v = np.array([ux, uy]) + F / (2 * rho)
+        ref = general_form(F, np.outer(v, F) + np.outer(F, v))
+        assert np.allclose(Fa, ref, rtol=0, atol=1e-15)
+        m0, m1, m2 = moments9(Fa)                       # Table I: B_e = C_e = 1
+        assert abs(m0) < 1e-16 and np.allclose(m1, F, atol=1e-16)
+        assert np.allclose(m2, np.outer(v, F) + np.outer(F, v), atol=1e-16)
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.105])
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.5])
+def test_improved_scheme_is_eq31_first_form(sigma, tau):
+    # Eq. (31), first form = Eq. (12) with B = (1 - 1/2tau) F, C = (1 - 1/2tau)(v'F + Fv');
+    # sigma = 0 is Guo et al.'s scheme, Eq. (13)
+    rng = np.random.default_rng(5)
+    p = cs_params(scheme=lbm.SCHEME_IMPROVED, tau=tau, sigma=sigma, nx=3, ny=3)
+    for _ in range(30):
+        rho, ux, uy, Fx, Fy, s2 = _random_node(rng)
+        ueq, Fa = lbm.forcing(p, rho, ux, uy, Fx, Fy, s2)
+        F = np.array([Fx, Fy])
+        v = np.array([ux, uy]) + F / (2 * rho)
+        assert np.allclose(ueq, v, rtol=0, atol=1e-18)
+        vp = v + sigma * F / ((tau - 0.5) * s2)
+        Be = 1 - 1 / (2 * tau)
+        C = Be * (np.outer(vp, F) + np.outer(F, vp))
+        assert np.allclose(Fa, general_form(Be * F, C), rtol=0, atol=1e-15)
+        m0, m1, m2 = moments9(Fa)
+        assert abs(m0) < 1e-16 and np.allclose(m1, Be * F, atol=1e-16)
+        assert np.allclose(m2, C, atol=1e-16)
+
+
+def _noisy_slab(p, t=0.8, noise=0.01, seed=11):
+    c = th.maxwell_cs(t)
+    rho0 = synth.slab(p.nx, p.ny, c.rho_l, c.rho_g, p.nx / 4, 3 * p.nx / 4, 2.0, noise, seed)
+    return lbm.init_equilibrium(rho0)
+
+
+def test_shan_chen_equals_edm_at_tau_one():
+    # Sec. III.B: the two schemes differ only in the forcing velocity and coincide at tau = 1
+    p_sc = cs_params(scheme=lbm.SCHEME_SC, tau=1.0, nx=32, ny=16)
+    p_edm = cs_params(scheme=lbm.SCHEME_EDM, tau=1.0, nx=32, ny=16)
+    f1 = _noisy_slab(p_sc)
+    f2 = f1.copy()
+    assert lbm.step(p_sc, f1, 300)[0] == 0 and lbm.step(p_edm, f2, 300)[0] == 0
+    assert np.abs(f1 - f2).max() < 1e-13
+    # and they differ at tau != 1
+    p_sc.tau = p_edm.tau = 0.7
+    f1 = _noisy_slab(p_sc); f2 = f1.copy()
+    lbm.step(p_sc, f1, 300); lbm.step(p_edm, f2, 300)
+    assert np.abs(f1 - f2).max() > 1e-6
+
+
+# ---------------------------------------------------------------- invariants of Eq. (1)
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_rest_state(scheme):
+    p = cs_params(scheme=scheme, tau=0.7, sigma=0.1, nx=8, ny=5)
+    f = lbm.init_equilibrium(np.full((5, 8), 0.2))
+    st, _ = lbm.step(p, f, 50)
+    assert st == 0
+    rho, vx, vy, _ = lbm.moments(p, f)
+    assert np.all(vx == 0.0) and np.all(vy == 0.0)
+    assert np.all(f == f[:, :1, :1])                 # every node identical
+    assert np.abs(rho - 0.2).max() < 50 * 9 * 2.3e-16 * 0.2
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_mass_and_momentum_conservation(scheme):
+    p = cs_params(scheme=scheme, tau=1.0, sigma=0.1, nx=32, ny=16)
+    f = _noisy_slab(p)
+    m0, _ = lbm.mass(f)
+    steps = 400
+    assert lbm.step(p, f, steps)[0] == 0
+    m1, _ = lbm.mass(f)
+    assert abs(m1 - m0) < steps * f.shape[1] * f.shape[2] * 2.3e-16 * 0.4
+    jx = (f * EX[:, None, None]).sum()
+    jy = (f * EY[:, None, None]).sum()
+    assert abs(jx) < 1e-12 and abs(jy) < 1e-12
+
+
+def test_translation_invariance_bitwise():
+    p = cs_params(tau=0.8, sigma=0.1, nx=24, ny=12)
+    f = _noisy_slab(p)
+    g = np.roll(f, (5, 7), axis=(1, 2)).copy()
+    lbm.step(p, f, 40); lbm.step(p, g, 40)
+    assert np.array_equal(np.roll(f, (5, 7), axis=(1, 2)), g)
+
+
+def test_noise_free_slab_rows_identical():
+    p = cs_params(tau=0.8, sigma=0.1, nx=32, ny=6)
+    f = _noisy_slab(p, noise=0.0)
+    lbm.step(p, f, 200)
+    assert np.all(f == f[:, :1, :])
+
+
+def test_fixed_point_mass_is_exact_sum():
+    rng = np.random.default_rng(6)
+    f = rng.uniform(0.0, 0.1, (9, 7, 5))
+    m, fixed = lbm.mass(f)
+    rho = np.zeros((7, 5))
+    for a in range(9):
+        rho = rho + f[a]
+    exact = sum(int(np.rint(np.ldexp(r, 40))) for r in rho.ravel())
+    assert fixed == exact
+    assert abs(m - rho.sum()) < 1e-14
+
+
+# ---------------------------------------------------------------- textbook special cases
+
+def test_shear_wave_viscosity():
+    # uniform density (zero force): a shear wave decays as exp(-nu k^2 t), nu = c_s^2 (tau - 1/2)
+    N, tau = 64, 0.8
+    p = cs_params(t=0.8, tau=tau, nx=N, ny=3, sigma=0.1)
+    k = 2 * np.pi / N
+    x = np.arange(N)
+    uy = np.broadcast_to(1e-4 * np.sin(k * x), (3, N)).copy()
+    f = lbm.init_equilibrium(np.full((3, N), 0.02), None, uy)
+    amps = []
+    for t in (100, 600):
+        lbm.step(p, f, t - (0 if not amps else 100))
+        _, _, vy, _ = lbm.moments(p, f)
+        amps.append(2 * (vy[0] * np.sin(k * x)).mean())
+    rate = np.log(amps[0] / amps[1]) / 500
+    nu = CS2 * (tau - 0.5)
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+def test_sound_pulse_speed_and_direction():
+    # a right-running acoustic pulse moves in +x at c = sqrt(dp_EOS/drho) (Eqs. 5, 8)
+    N = 256
+    p = cs_params(t=1.5, tau=0.8, nx=N, ny=3, sigma=0.0)
+    rho0 = 0.1
+    h = 1e-7
+    c = np.sqrt((lbm.p_eos(p, rho0 + h) - lbm.p_eos(p, rho0 - h)) / (2 * h))
+    x = np.arange(N, dtype=float)
+    d = 1e-4 * np.exp(-((x - 60) / 6.0) ** 2)
+    rho = np.broadcast_to(rho0 + d, (3, N)).copy()
+    ux = np.broadcast_to(c * d / rho0, (3, N)).copy()
+    f = lbm.init_equilibrium(rho, ux, None)
+    steps = 150
+    lbm.step(p, f, steps)
+    r, _, _, _ = lbm.moments(p, f)
+    dr = r[0] - rho0
+    i = int(np.argmax(dr))                       # peak of the right-running pulse
+    y0, y1, y2 = dr[i - 1], dr[i], dr[i + 1]
+    xc = i + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
+    assert xc > 60                               # it ran in +x
+    assert abs((xc - 60) / steps / c - 1) < 0.01
+
+
+# ---------------------------------------------------------------- coexistence (Sec. IV.B)
+
+def _flat(t, sigma, tau, scheme=lbm.SCHEME_IMPROVED, steps=10000, nx=100):
+    c = th.maxwell_cs(t)
+    p = cs_params(t=t, tau=tau, sigma=sigma, scheme=scheme, nx=nx, ny=3)
+    f = lbm.init_equilibrium(synth.slab(nx, 3, c.rho_l, c.rho_g, nx / 4, 3 * nx / 4, 2.0))
+    st, _ = lbm.step(p, f, steps)
+    assert st == 0
+    prof = lbm.moments(p, f)[0].mean(0)
+    return prof[nx // 2], prof[0]
+
+
+@pytest.mark.parametrize("sigma,eps,tol_g", [(0.0, 0.0, 0.002), (0.0625, 1.0, 0.02), (0.125, 2.0, 0.02)])
+def test_flat_interface_matches_mechanical_stability(sigma, eps, tol_g):
+    # Fig. 5: the improved scheme follows Eq. (26) with eps = 16 sigma (100-wide flat interface)
+    rl, rg = _flat(0.8, sigma, 1.0)
+    ref = th.mechanical_cs(0.8, eps)
+    assert abs(rg / ref.rho_g - 1) < tol_g
+    assert abs(rl / ref.rho_l - 1) < 1e-3
+
+
+def test_flat_interface_sigma0105_near_maxwell():
+    # Fig. 6: sigma = 0.105 (eps = 1.68) approximates the Maxwell construction
+    for t, tol in ((0.8, 0.01), (0.7, 0.04)):
+        rl, rg = _flat(t, 0.105, 1.0)
+        m = th.maxwell_cs(t)
+        assert abs(rg / m.rho_g - 1) < tol
+        assert abs(rl / m.rho_l - 1) < 1e-3
+
+
+def test_tau_dependence_by_scheme():
+    # Eqs. (32)-(33): the improved scheme's coexistence does not depend on tau;
+    # Eq. (20): Shan-Chen's does (its tau^2 FF/rho term grows with tau)
+    g06 = _flat(0.8, 0.105, 0.6, steps=12000)[1]
+    g10 = _flat(0.8, 0.105, 1.0)[1]
+    assert abs(g06 / g10 - 1) < 0.01
+    s08 = _flat(0.8, 0.0, 0.8, scheme=lbm.SCHEME_SC)[1]
+    s13 = _flat(0.8, 0.0, 1.3, scheme=lbm.SCHEME_SC)[1]
+    assert s13 / s08 > 1.5
+
+
+# ---------------------------------------------------------------- failure detection
+
+def test_divergence_and_invalid_input():
+    p = cs_params(nx=8, ny=8)
+    f = lbm.init_equilibrium(np.full((8, 8), 0.1))
+    f[3, 2, 2] = np.nan
+    st, d = lbm.step(p, f, 10)
+    assert st == lbm.EDIVERGED and d == 0
+    f = lbm.init_equilibrium(np.full((8, 8), 0.1))
+    f[0, 4, 4] = -1.0                              # negative density at one node
+    st, d = lbm.step(p, f, 10)
+    assert st == lbm.EDIVERGED and d == 0
+    p.tau = 0.5
+    assert lbm.step(p, lbm.init_equilibrium(np.full((8, 8), 0.1)), 1)[0] == lbm.EINVAL
+
+
+def test_laplace_law_droplets():
+    # Laplace's law: the pressure jump across a droplet interface is linear in 1/R
+    # with no offset (paper silent; spec validation of the oracle)
+    Tc, _ = th.critical_cs()
+    c = th.maxwell_cs(0.8)
+    N = 64
+    pts = []
+    for R in (10, 14, 20):
+        p = lbm.Params(nx=N, ny=N, tau=1.0, T=0.8 * Tc, sigma=0.105)
+        f = lbm.init_equilibrium(synth.droplet(N, N, c.rho_l, c.rho_g, R))
+        assert lbm.step(p, f, 5000)[0] == 0
+        r, _, _, pp = lbm.moments(p, f)
+        rl = r[N // 2 - 1:N // 2 + 2, N // 2 - 1:N // 2 + 2].mean()
+        rg = r[0, 0]
+        Re = np.sqrt((r.sum() - rg * N * N) / (np.pi * (rl - rg)))     # equimolar radius
+        pts.append((1.0 / Re, pp[N // 2, N // 2] - pp[0, 0]))
+    x, y = np.array(pts).T
+    A = np.vstack([x, np.ones_like(x)]).T
+    (slope, icpt), res, _, _ = np.linalg.lstsq(A, y, rcond=None)
+    r2 = 1 - res[0] / ((y - y.mean()) ** 2).sum()
+    assert slope > 0 and r2 > 0.999
+    assert abs(icpt) < 0.05 * y.max()
