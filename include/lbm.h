@@ -1,0 +1,195 @@
+/*
+ * lbm.h -- C ABI of the MI355X pseudopotential lattice Boltzmann library.
+ *
+ * The library advances the D2Q9 BGK lattice Boltzmann equation with the
+ * Shan-Chen pseudopotential interaction force on AMD Instinct MI355X
+ * (gfx950).  Method: Q. Li, K. H. Luo, X. J. Li, "Forcing scheme in
+ * pseudopotential lattice Boltzmann model for multiphase flows",
+ * arXiv:1204.4098.  One time step (lbm_step) is, at every node:
+ *
+ *   1. streaming (pull form of Eq. 1):   f_a(x, t) = f*_a(x - e_a, t - 1)
+ *   2. moments:                          rho = sum f_a, u = sum f_a e_a / rho
+ *   3. potential, Eq. (8) with c = 1:    psi = sqrt(2 (p_EOS(rho) - rho/3) / G)
+ *      p_EOS is Carnahan-Starling (Eq. 23) or Peng-Robinson (standard form)
+ *   4. interaction force, Eq. (3):       F = -G psi(x) sum_a w(|e_a|^2) psi(x + e_a) e_a,
+ *                                        w(1) = 1/3, w(2) = 1/12
+ *   5. forcing scheme and BGK collision, Eqs. (1), (2), (9)-(11), (31):
+ *        Shan-Chen:  u_eq = u + tau F / rho, no forcing term
+ *        EDM:        u_eq = u, F_a = f_eq(rho, u + F/rho) - f_eq(rho, u)
+ *        improved:   u_eq = v = u + F / (2 rho),
+ *                    F_a = w_a (1 - 1/(2 tau)) [(e_a - v')/c_s^2 + (e_a.v') e_a / c_s^4] . F,
+ *                    v' = v + sigma F / ((tau - 1/2) psi^2)   (sigma = 0: Guo et al.)
+ *        f*_a = f_a - (f_a - f_eq_a(rho, u_eq)) / tau + F_a
+ *
+ * Units: c = delta_t = 1, c_s^2 = 1/3.  Boundaries are periodic in x and y.
+ * Directions: e0=(0,0) e1=(1,0) e2=(0,1) e3=(-1,0) e4=(0,-1)
+ *             e5=(1,1) e6=(-1,1) e7=(-1,-1) e8=(1,-1).
+ *
+ * Host arrays are row-major [y][x] (x fastest); population arrays are
+ * [a][y][x].  Device memory is owned by the caller: the library never
+ * allocates device memory; it works inside a caller-provided workspace whose
+ * size the *_workspace_bytes functions report.  The workspace must stay
+ * allocated, and must not be used by anyone else, until the matching
+ * *_destroy call.  All work is enqueued on the caller's HIP stream
+ * (hipStream_t passed as void*; NULL = the null stream).  A context must not
+ * be used from two threads at once.
+ *
+ * Every function returns an int status: LBM_OK (0) or a negative error code
+ * (lbm_strerror gives its text).  No C++ exception crosses this boundary.
+ * A non-finite or non-positive density, or a non-positive argument of the
+ * square root of Eq. (8), during a step marks the run as diverged: kernels
+ * record the first such step on the device, and the next call that
+ * synchronises (lbm_status, lbm_moments, lbm_mass, lbm_get_populations,
+ * lbm_batch_coexistence) reports it.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;      /* one lattice; opaque, host-side */
+typedef struct lbm_batch lbm_batch;  /* many independent lattices; opaque */
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* invalid argument or parameter */
+  LBM_EPSI = -2,        /* initial density outside the EOS range: 2(p - rho/3)/G <= 0 */
+  LBM_EDIVERGED = -3,   /* the run diverged (see lbm_status) */
+  LBM_EHIP = -4,        /* a HIP runtime call failed */
+  LBM_ENOSPACE = -5,    /* workspace smaller than *_workspace_bytes reports */
+  LBM_ENOTSUP = -6      /* request not supported by this build */
+};
+
+enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 };
+enum { LBM_SCHEME_SHANCHEN = 0, LBM_SCHEME_EDM = 1, LBM_SCHEME_IMPROVED = 2 };
+/* Storage of populations: FP64, or deviations d_a = f_a - w_a rho_ref stored
+ * in FP32 / FP16 with FP32 collision arithmetic (the EOS and psi stay FP64). */
+enum { LBM_PREC_F64 = 0, LBM_PREC_F32DEV = 1, LBM_PREC_F16DEV = 2 };
+
+typedef struct {
+  int32_t nx, ny;    /* lattice size, periodic; 3 <= nx, ny; nx*ny < 2^31 */
+  double tau;        /* relaxation time, Eq. (1); > 0.5 */
+  double G;          /* interaction strength, Eq. (3); nonzero (the paper: -1) */
+  int32_t eos;       /* LBM_EOS_* */
+  double a, b, R;    /* EOS constants (C-S: a=1, b=4, R=1 in the paper) */
+  double T;          /* absolute temperature (use lbm_critical_point for T/Tc) */
+  double omega;      /* acentric factor (Peng-Robinson only) */
+  int32_t scheme;    /* LBM_SCHEME_* */
+  double sigma;      /* sigma of the improved scheme, Eq. (31); ignored otherwise */
+  int32_t precision; /* LBM_PREC_* */
+  double rho_ref;    /* reference density of deviation storage; NaN = mean of rho0 */
+} lbm_params;
+
+/* ---- thermodynamics (host only; no GPU needed) ---------------------------- */
+
+/* Critical point of the EOS (dp/drho = d2p/drho2 = 0; Peng-Robinson with
+ * alpha = 1).  Sec. III.C gives Tc ~ 0.094, rho_c = 0.13044 for C-S a=1, b=4, R=1. */
+int lbm_critical_point(int32_t eos, double a, double b, double R, double omega,
+                       double* Tc, double* rho_c);
+
+/* Maxwell-construction coexistence densities, Eq. (7), at absolute T < Tc. */
+int lbm_maxwell(int32_t eos, double a, double b, double R, double omega, double T,
+                double* rho_l, double* rho_g, double* p0);
+
+/* Equation of state p_EOS(rho) at the parameters' T (host, FP64). */
+int lbm_pressure(const lbm_params* p, double rho, double* p_out);
+
+/* ---- single lattice -------------------------------------------------------- */
+
+/* Bytes of device workspace lbm_init needs for these parameters. */
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* Create a context.  rho0 (host, ny*nx) is the initial density; ux0/uy0
+ * (host, ny*nx, nullable = 0) the initial velocity; populations start at
+ * f_eq(rho0, u0) (Eq. 2).  dev_workspace must be 256-byte aligned.
+ * Returns LBM_EPSI when some rho0 lies outside the EOS range. */
+int lbm_init(const lbm_params* p, const double* rho0, const double* ux0, const double* uy0,
+             void* dev_workspace, size_t ws_bytes, void* hip_stream, lbm_ctx** out);
+
+/* Enqueue n time steps on the context's stream (asynchronous). */
+int lbm_step(lbm_ctx* c, int64_t n);
+
+/* Synchronise; *step = steps taken so far, *diverged_at = first diverged step
+ * or -1.  Returns LBM_EDIVERGED if the run diverged, else LBM_OK. */
+int lbm_status(lbm_ctx* c, int64_t* step, int64_t* diverged_at);
+
+/* Macroscopic fields of the current state into host arrays (ny*nx each,
+ * nullable): rho, actual velocity v = u + F/(2 rho) (Table I), and pressure
+ * p = p_EOS(rho) (Eqs. 5 and 8).  Synchronous. */
+int lbm_moments(lbm_ctx* c, double* rho, double* vx, double* vy, double* p);
+
+/* Same, into device arrays (ny*nx each, FP64, non-null), asynchronous. */
+int lbm_moments_device(lbm_ctx* c, double* rho, double* vx, double* vy, double* p);
+
+/* Total mass: fixed[0..1] = the 128-bit integer sum over nodes of
+ * round-to-nearest-even(rho * 2^40) as (low, high) 64-bit words, with
+ * rho = sum_a f_a summed in direction order 0..8 in FP64 (populations decoded
+ * to FP64 first); *mass = FP64 sum.  Either pointer may be NULL.  Synchronous. */
+int lbm_mass(lbm_ctx* c, int64_t* fixed, double* mass);
+
+/* Current populations f_a(x, t) decoded to FP64, host array 9*ny*nx [a][y][x]. */
+int lbm_get_populations(lbm_ctx* c, double* f, int64_t* step);
+
+/* Replace the state by f (host 9*ny*nx), re-encoded to the storage type with
+ * round-to-nearest-even; sets the step counter and clears divergence. */
+int lbm_set_populations(lbm_ctx* c, const double* f, int64_t step);
+
+/* Bitwise checkpoint of the raw storage plus header (step, parameters). */
+int lbm_state_bytes(lbm_ctx* c, size_t* bytes);
+int lbm_save_state(lbm_ctx* c, void* host_buf, size_t bytes);
+int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes);
+
+/* Tiles: a work-group of 64*waves threads owns a strip of 64*waves columns and
+ * marches over `rows` rows.  lbm_tune times the candidates on the current
+ * state (without advancing it) and keeps the fastest; results are cached per
+ * (nx, ny, precision) for the process.  waves in {1, 2, 4}, rows in [1, 128]. */
+int lbm_tune(lbm_ctx* c, int32_t* waves, int32_t* rows);
+int lbm_set_tile(lbm_ctx* c, int32_t waves, int32_t rows);
+int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows);
+
+/* Replay n steps through captured HIP graphs of k steps each (k even, >= 2;
+ * 0 disables).  Results are bitwise identical to eager launches. */
+int lbm_set_graph_steps(lbm_ctx* c, int32_t k);
+
+/* Raw device addresses of the two population buffers (for timing and
+ * profiling tools) and which one holds the current state (0 or 1). */
+int lbm_device_buffers(lbm_ctx* c, void** buf0, void** buf1, int32_t* current);
+
+int lbm_destroy(lbm_ctx* c);
+const char* lbm_strerror(int status);
+
+/* ---- batch of independent lattices ---------------------------------------- */
+
+/* nruns parameter sets p[0..nruns-1] (one precision for all), initial
+ * densities rho0[i] (host, p[i].ny * p[i].nx each).  One persistent kernel
+ * launch advances every run by one step; a diverged run is frozen at the
+ * step it diverged and the others continue unchanged. */
+int lbm_batch_workspace_bytes(int32_t nruns, const lbm_params* p, size_t* bytes);
+int lbm_batch_init(int32_t nruns, const lbm_params* p, const double* const* rho0,
+                   void* dev_workspace, size_t ws_bytes, void* hip_stream, lbm_batch** out);
+int lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Coexistence densities of flat-interface runs: rho_l = mean density over y
+ * of the column at x = nx/2, rho_g = the same at x = 0 (slab in [nx/4, 3nx/4)).
+ * status[i] = LBM_OK or LBM_EDIVERGED; diverged_at[i] = first diverged step or
+ * -1.  Arrays of nruns (nullable).  Synchronous. */
+int lbm_batch_coexistence(lbm_batch* b, double* rho_l, double* rho_g, int32_t* status,
+                          int64_t* diverged_at);
+int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double* vy, double* p);
+int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f);
+int lbm_batch_tune(lbm_batch* b, int32_t* waves, int32_t* rows);
+int lbm_batch_set_tile(lbm_batch* b, int32_t waves, int32_t rows);
+int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k);
+/* Lattice updates per step summed over runs that are still active. */
+int lbm_batch_nodes(lbm_batch* b, int64_t* nodes);
+int lbm_batch_destroy(lbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,414 @@
+// Device code of the fused pseudopotential D2Q9 step for gfx950.
+//
+// One work-group owns a strip of SW = 64*NW lattice columns (one column per
+// thread) and a chunk of L rows, and marches up the chunk one row at a time:
+//
+//   * streaming is done on load (pull): f_a(x, y) = f*_a(x - e_a, y - e_a)
+//     from the source buffer (paper Eq. 1);
+//   * each loaded row gives rho and, in FP64, psi^2 = 2 (p_EOS - rho/3)/G
+//     (Eqs. 8, 23); psi goes to a 4-row ring in LDS;
+//   * the row below is then complete (psi at y-1, y, y+1), so its force
+//     (Eq. 3), forcing scheme (Eqs. 9-11, 31) and BGK collision (Eqs. 1, 2)
+//     are computed and its 9 populations stored, coalesced, to the
+//     destination buffer at the same node.
+//
+// psi of the two halo columns x0-1 and x0+SW is computed once per chunk in a
+// prologue; the halo rows y0-1 and y0+L are recomputed by the chunks on
+// either side.  Populations are read once from HBM and written once (the
+// neighbour strips' halo reads hit L2), so a step moves 2*9*sizeof(storage)
+// bytes per node.  The paper gives no kernel design; this layout is ours.
+//
+// Storage: FP64 populations, or deviations s_a = f_a - w_a rho_ref in FP32 /
+// FP16 with FP32 collision arithmetic.  The EOS, psi and force stencil are
+// always evaluated in FP64.
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+constexpr int LMAX = 128;  // largest chunk height (rows) a work-group marches
+
+// Per-lattice constants, prepared on the host.
+struct RunDev {
+  int32_t nx, ny, pitch, eos;
+  int64_t plane;            // elements per direction plane (ny * pitch)
+  int64_t off;              // element offset of this lattice in the population pool
+  double RT, c1, c2;        // EOS constants (see EosConst)
+  double two_over_G, mG;    // 2/G and -G
+  double inv_tau;
+  // forcing scheme in general form: u_eq = u + c_eq F/rho,
+  // F_a = w_a [3 Be e.F + Ce (9 (e.vf)(e.F) - 3 vf.F)], vf = u + c_f F/rho + sig F/psi^2
+  double c_eq, c_f, sig, Be, Ce;
+  double rho_ref;           // deviation reference density (0 for FP64 storage)
+  int32_t run, pad;
+};
+
+// A tile of the batched launch.
+struct Item {
+  int32_t run, x0, y0, ncols, nrows, pad;
+};
+
+template <typename S> struct Store;
+template <> struct Store<double> {
+  using R = double;
+  static __device__ __forceinline__ R ld(const double* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(double* p, R v) { __builtin_nontemporal_store(v, p); }
+};
+template <> struct Store<float> {
+  using R = float;
+  static __device__ __forceinline__ R ld(const float* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(float* p, R v) { __builtin_nontemporal_store(v, p); }
+};
+template <> struct Store<__half> {
+  using R = float;
+  static __device__ __forceinline__ R ld(const __half* p) {
+    return __half2float(*p);
+  }
+  static __device__ __forceinline__ void st(__half* p, R v) { *p = __float2half_rn(v); }
+};
+
+__device__ constexpr int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// Pull the 9 populations of node (x, y) from the post-collision field.
+template <typename S>
+__device__ __forceinline__ void pull9(const S* __restrict__ src, const RunDev& d, int x, int y,
+                                      typename Store<S>::R (&f)[9]) {
+  const int xm = x == 0 ? d.nx - 1 : x - 1;
+  const int xp = x == d.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? d.ny - 1 : y - 1;
+  const int yp = y == d.ny - 1 ? 0 : y + 1;
+  const int64_t P = d.plane;
+  const int64_t r0 = (int64_t)y * d.pitch, rm = (int64_t)ym * d.pitch, rp = (int64_t)yp * d.pitch;
+  using T = Store<S>;
+  f[0] = T::ld(src + r0 + x);
+  f[1] = T::ld(src + P + r0 + xm);
+  f[2] = T::ld(src + 2 * P + rm + x);
+  f[3] = T::ld(src + 3 * P + r0 + xp);
+  f[4] = T::ld(src + 4 * P + rp + x);
+  f[5] = T::ld(src + 5 * P + rm + xm);
+  f[6] = T::ld(src + 6 * P + rm + xp);
+  f[7] = T::ld(src + 7 * P + rp + xp);
+  f[8] = T::ld(src + 8 * P + rp + xm);
+}
+
+// Density deviation sum_a s_a in the arithmetic type (pairwise order).
+template <typename R>
+__device__ __forceinline__ R sum9(const R (&s)[9]) {
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
+}
+
+// psi^2 = 2 (p_EOS(rho) - rho/3) / G in FP64 (Eq. 8 with Eq. 23 or Peng-Robinson).
+__device__ __forceinline__ double psi2_of(double rho, const RunDev& d) {
+  double p;
+  if (d.eos == 0) {
+    const double e = d.c1 * rho, m = 1.0 - e;
+    p = rho * d.RT * (1.0 + e * (1.0 + e * (1.0 - e))) / (m * m * m) - d.c2 * rho * rho;
+  } else {
+    p = rho * d.RT / (1.0 - d.c1 * rho) - d.c2 * rho * rho / (1.0 + d.c1 * rho * (2.0 - d.c1 * rho));
+  }
+  return (p - rho * (1.0 / 3.0)) * d.two_over_G;
+}
+
+__device__ __forceinline__ double pressure_of(double rho, const RunDev& d) {
+  if (d.eos == 0) {
+    const double e = d.c1 * rho, m = 1.0 - e;
+    return rho * d.RT * (1.0 + e * (1.0 + e * (1.0 - e))) / (m * m * m) - d.c2 * rho * rho;
+  }
+  return rho * d.RT / (1.0 - d.c1 * rho) - d.c2 * rho * rho / (1.0 + d.c1 * rho * (2.0 - d.c1 * rho));
+}
+
+// Interaction force of Eq. (3) from the 3x3 psi neighbourhood (row-major:
+// s = y-1, c = y, n = y+1; index 0 = x-1, 1 = x, 2 = x+1), w(1)=1/3, w(2)=1/12.
+__device__ __forceinline__ void force3x3(const double* rs, const double* rc, const double* rn, int i,
+                                         double mG, double& Fx, double& Fy) {
+  constexpr double w1 = 1.0 / 3.0, w2 = 1.0 / 12.0;
+  const double dNE = rn[i + 1] - rs[i - 1];   // psi(x+e5) - psi(x-e5)
+  const double dNW = rn[i - 1] - rs[i + 1];   // psi(x+e6) - psi(x-e6)
+  const double Sx = w1 * (rc[i + 1] - rc[i - 1]) + w2 * (dNE - dNW);
+  const double Sy = w1 * (rn[i] - rs[i]) + w2 * (dNE + dNW);
+  const double c = mG * rc[i];
+  Fx = c * Sx;
+  Fy = c * Sy;
+}
+
+// BGK collision with the forcing scheme in general form (see RunDev).
+template <typename R>
+__device__ __forceinline__ void collide(R (&s)[9], R drho, R rho, R jx, R jy, R Fx, R Fy,
+                                        R inv_psi2, const RunDev& d) {
+  const R inv_rho = R(1) / rho;
+  const R ux = jx * inv_rho, uy = jy * inv_rho;
+  const R Fr_x = Fx * inv_rho, Fr_y = Fy * inv_rho;
+  const R wx = ux + R(d.c_eq) * Fr_x, wy = uy + R(d.c_eq) * Fr_y;
+  const R sg = R(d.sig) * inv_psi2;
+  const R vx = ux + R(d.c_f) * Fr_x + sg * Fx, vy = uy + R(d.c_f) * Fr_y + sg * Fy;
+  const R om = R(d.inv_tau), Be3 = R(3.0 * d.Be), Ce = R(d.Ce);
+  const R usq = R(1.5) * (wx * wx + wy * wy);
+  const R vF3 = R(3) * (vx * Fx + vy * Fy);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const R w = R(kW[a]);
+    const R eu = R(kEX[a]) * wx + R(kEY[a]) * wy;
+    const R seq = w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
+    const R eF = R(kEX[a]) * Fx + R(kEY[a]) * Fy;
+    const R ev = R(kEX[a]) * vx + R(kEY[a]) * vy;
+    const R Fa = w * (Be3 * eF + Ce * (R(9) * ev * eF - vF3));
+    s[a] = s[a] + om * (seq - s[a]) + Fa;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R mom_x(const R (&s)[9]) {
+  return ((s[1] - s[3]) + (s[5] - s[7])) + (s[8] - s[6]);
+}
+template <typename R>
+__device__ __forceinline__ R mom_y(const R (&s)[9]) {
+  return ((s[2] - s[4]) + (s[5] - s[7])) + (s[6] - s[8]);
+}
+
+// One tile: columns [x0, x0+ncols), rows [y0, y0+nrows).  All threads of the
+// block call it (barriers inside); ring is [4][SW+2], haloL/haloR [LMAX+2].
+template <typename S, int NW>
+__device__ __forceinline__ void tile_step(const S* __restrict__ src, S* __restrict__ dst,
+                                          const RunDev& d, int x0, int y0, int ncols, int nrows,
+                                          unsigned long long step,
+                                          unsigned long long* __restrict__ flag,
+                                          double (*ring)[64 * NW + 2], double* haloL,
+                                          double* haloR) {
+  using T = Store<S>;
+  using R = typename T::R;
+  constexpr int SW = 64 * NW;
+  const int tid = threadIdx.x;
+  const bool act = tid < ncols;
+  const int x = x0 + tid;
+  const int xl = x0 == 0 ? d.nx - 1 : x0 - 1;
+  const int xr = x0 + ncols >= d.nx ? 0 : x0 + ncols;
+  const double rref = d.rho_ref;
+  bool bad = false;
+
+  // prologue: psi of the two halo columns for rows y0-1 .. y0+nrows
+  for (int i = tid; i < 2 * (nrows + 2); i += SW) {
+    const int k = i >> 1;
+    int yy = y0 - 1 + k;
+    yy = yy < 0 ? yy + d.ny : (yy >= d.ny ? yy - d.ny : yy);
+    R f[9];
+    pull9<S>(src, d, (i & 1) ? xr : xl, yy, f);
+    const double rho = rref + double(sum9(f));
+    const double p2 = psi2_of(rho, d);
+    ((i & 1) ? haloR : haloL)[k] = sqrt(p2);
+  }
+  __syncthreads();
+
+  // preload rows y0-1 (ring slot 0) and y0 (slot 1)
+  R fc[9];
+  double psi2c = 0.0;
+  if (act) {
+    R f[9];
+    pull9<S>(src, d, x, y0 == 0 ? d.ny - 1 : y0 - 1, f);
+    ring[0][tid + 1] = sqrt(psi2_of(rref + double(sum9(f)), d));
+    pull9<S>(src, d, x, y0, fc);
+    psi2c = psi2_of(rref + double(sum9(fc)), d);
+    ring[1][tid + 1] = sqrt(psi2c);
+  }
+  if (tid == 0) {
+    ring[0][0] = haloL[0];
+    ring[0][ncols + 1] = haloR[0];
+    ring[1][0] = haloL[1];
+    ring[1][ncols + 1] = haloR[1];
+  }
+
+  for (int j = 0; j < nrows; ++j) {
+    const int y = y0 + j;
+    const int yn = y + 1 == d.ny ? 0 : y + 1;
+    const int sl = (j + 2) & 3;
+    R fn[9];
+    double psi2n = 0.0;
+    if (act) {
+      pull9<S>(src, d, x, yn, fn);
+      psi2n = psi2_of(rref + double(sum9(fn)), d);
+      ring[sl][tid + 1] = sqrt(psi2n);
+    }
+    if (tid == 0) {
+      ring[sl][0] = haloL[j + 2];
+      ring[sl][ncols + 1] = haloR[j + 2];
+    }
+    __syncthreads();
+    if (act) {
+      double Fx, Fy;
+      force3x3(ring[j & 3], ring[(j + 1) & 3], ring[sl], tid + 1, d.mG, Fx, Fy);
+      const R drho = sum9(fc);
+      const double rho64 = rref + double(drho);
+      bad |= !(psi2c > 0.0) || !(rho64 > 0.0);
+      collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), R(1.0 / psi2c), d);
+      const int64_t o = (int64_t)y * d.pitch + x;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) T::st(dst + a * d.plane + o, fc[a]);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) fc[a] = fn[a];
+      psi2c = psi2n;
+    }
+  }
+  // divergence: one atomic per wave that saw a bad node
+  if (__ballot(bad) != 0 && __lane_id() == 0) atomicMin(flag, step);
+}
+
+// XCD-aware block order: consecutive tiles go to the same XCD (blocks are
+// dispatched round-robin over the 8 XCDs), so halo rows/columns shared by
+// neighbouring tiles are found in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7, k = b & 7, i = b >> 3;
+  return k * q + (k < r ? k : r) + i;
+}
+
+template <typename S, int NW>
+__global__ __launch_bounds__(64 * NW) void k_step(const S* __restrict__ src, S* __restrict__ dst,
+                                                  RunDev d, int L, int nstrips,
+                                                  const unsigned long long* stepbase,
+                                                  unsigned long long steplocal,
+                                                  unsigned long long* flag) {
+  __shared__ double ring[4][64 * NW + 2];
+  __shared__ double haloL[LMAX + 2], haloR[LMAX + 2];
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int sy = t / nstrips, sx = t - sy * nstrips;
+  const int x0 = sx * 64 * NW, y0 = sy * L;
+  const int ncols = min(64 * NW, d.nx - x0), nrows = min(L, d.ny - y0);
+  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
+  if (*flag < step) return;  // diverged at an earlier step: the run is frozen
+  tile_step<S, NW>(src, dst, d, x0, y0, ncols, nrows, step, flag, ring, haloL, haloR);
+}
+
+// Persistent batched step: blocks of XCD k walk the k-th contiguous eighth of
+// the work list.  Grid must be a multiple of 8.
+template <typename S, int NW>
+__global__ __launch_bounds__(64 * NW) void k_batch_step(const S* __restrict__ src,
+                                                        S* __restrict__ dst,
+                                                        const RunDev* __restrict__ runs,
+                                                        const Item* __restrict__ items, int nitems,
+                                                        const unsigned long long* stepbase,
+                                                        unsigned long long steplocal,
+                                                        unsigned long long* flags) {
+  __shared__ double ring[4][64 * NW + 2];
+  __shared__ double haloL[LMAX + 2], haloR[LMAX + 2];
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, nb = gridDim.x >> 3;
+  const int lo = (int)((int64_t)nitems * xcd / 8), hi = (int)((int64_t)nitems * (xcd + 1) / 8);
+  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
+  for (int i = lo + slot; i < hi; i += nb) {
+    const Item it = items[i];
+    const RunDev d = runs[it.run];
+    if (flags[it.run] < step) continue;
+    tile_step<S, NW>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
+                     &flags[it.run], ring, haloL, haloR);
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+// Graph helper: advance the device step counter after k steps.
+__global__ void k_counter_add(unsigned long long* ctr, unsigned long long k) { *ctr += k; }
+__global__ void k_counter_set(unsigned long long* ctr, unsigned long long v) { *ctr = v; }
+
+// ---- diagnostics (rare; simple one-node-per-thread kernels) ---------------
+
+// Pass 1: rho, u = j/rho and psi at every node (rho/ux/uy/psi planes, [y][x]).
+template <typename S>
+__global__ void k_moments1(const S* __restrict__ src, RunDev d, double* rho, double* ux,
+                           double* uy, double* psi) {
+  using R = typename Store<S>::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= d.nx) return;
+  R f[9];
+  pull9<S>(src, d, x, y, f);
+  const R drho = sum9(f);
+  const double r = d.rho_ref + double(drho);
+  const int64_t o = (int64_t)y * d.nx + x;
+  rho[o] = r;
+  ux[o] = double(mom_x(f) / R(r));
+  uy[o] = double(mom_y(f) / R(r));
+  psi[o] = sqrt(psi2_of(r, d));
+}
+
+// Pass 2: v = u + F/(2 rho) (Table I, actual velocity) and p = p_EOS(rho).
+__global__ void k_moments2(RunDev d, const double* __restrict__ psi, const double* rho, double* vx,
+                           double* vy, double* p) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= d.nx) return;
+  const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const double* rs = psi + (int64_t)ym * d.nx;
+  const double* rc = psi + (int64_t)y * d.nx;
+  const double* rn = psi + (int64_t)yp * d.nx;
+  const double s[3] = {rs[xm], rs[x], rs[xp]}, c[3] = {rc[xm], rc[x], rc[xp]},
+               n[3] = {rn[xm], rn[x], rn[xp]};
+  double Fx, Fy;
+  force3x3(s, c, n, 1, d.mG, Fx, Fy);
+  const int64_t o = (int64_t)y * d.nx + x;
+  const double r = rho[o];
+  vx[o] += Fx / (2.0 * r);
+  vy[o] += Fy / (2.0 * r);
+  p[o] = pressure_of(r, d);
+}
+
+// Decode one stored population to FP64 exactly as the host decoder does:
+// f = s + (w * rho_ref), two separately rounded operations.
+template <typename S>
+__device__ __forceinline__ double decode(S v, int a, double rref) {
+#pragma clang fp contract(off)
+  const double wr = kW[a] * rref;
+  return double(typename Store<S>::R(v)) + wr;
+}
+template <>
+__device__ __forceinline__ double decode<double>(double v, int, double) {
+  return v;
+}
+template <>
+__device__ __forceinline__ double decode<__half>(__half v, int a, double rref) {
+#pragma clang fp contract(off)
+  const double wr = kW[a] * rref;
+  return double(__half2float(v)) + wr;
+}
+
+// Mass: per block, sum of round-to-nearest-even(rho * 2^40) (exact, int64) and
+// the FP64 sum; rho = sum_a f_a in direction order of the decoded populations.
+template <typename S>
+__global__ __launch_bounds__(256) void k_mass(const S* __restrict__ src, RunDev d,
+                                              long long* part_i, double* part_d) {
+  __shared__ long long si[256];
+  __shared__ double sd[256];
+  const int64_t n = (int64_t)d.nx * d.ny;
+  long long acc_i = 0;
+  double acc_d = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+    const int y = (int)(k / d.nx), x = (int)(k - (int64_t)y * d.nx);
+    const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+    const int64_t P = d.plane;
+    const int64_t r0 = (int64_t)y * d.pitch, rm = (int64_t)ym * d.pitch, rp = (int64_t)yp * d.pitch;
+    const int64_t idx[9] = {r0 + x,          P + r0 + xm,     2 * P + rm + x,
+                            3 * P + r0 + xp, 4 * P + rp + x,  5 * P + rm + xm,
+                            6 * P + rm + xp, 7 * P + rp + xp, 8 * P + rp + xm};
+    double r = 0.0;
+    for (int a = 0; a < 9; ++a) r += decode<S>(src[idx[a]], a, d.rho_ref);
+    acc_i += __double2ll_rn(r * 1099511627776.0);  // 2^40, exact scaling
+    acc_d += r;
+  }
+  si[threadIdx.x] = acc_i;
+  sd[threadIdx.x] = acc_d;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      si[threadIdx.x] += si[threadIdx.x + s];
+      sd[threadIdx.x] += sd[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part_i[blockIdx.x] = si[0];
+    part_d[blockIdx.x] = sd[0];
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,1089 @@
+// Host side of the library: contexts, launches, graphs, tile tuning, batch
+// runs and the C ABI declared in include/lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int kEXh[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kEYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const double kWh[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                       1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+constexpr size_t kAlign = 256;
+constexpr int kMassBlocks = 1024;
+constexpr unsigned long long kNoDiv = ~0ull;
+
+#define HIPCHK(x)                        \
+  do {                                   \
+    if ((x) != hipSuccess) return LBM_EHIP; \
+  } while (0)
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+int esize_of(int prec) { return prec == LBM_PREC_F64 ? 8 : prec == LBM_PREC_F32DEV ? 4 : 2; }
+int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+
+int validate(const lbm_params& p) {
+  if (p.nx < 3 || p.ny < 3) return LBM_EINVAL;
+  if ((int64_t)p.nx * p.ny >= (1ll << 31)) return LBM_EINVAL;
+  if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return LBM_EINVAL;
+  if (!(p.G != 0.0) || !std::isfinite(p.G)) return LBM_EINVAL;
+  if (p.eos != LBM_EOS_CS && p.eos != LBM_EOS_PR) return LBM_EINVAL;
+  if (p.scheme < LBM_SCHEME_SHANCHEN || p.scheme > LBM_SCHEME_IMPROVED) return LBM_EINVAL;
+  if (p.precision < LBM_PREC_F64 || p.precision > LBM_PREC_F16DEV) return LBM_EINVAL;
+  if (!(p.a > 0) || !(p.b > 0) || !(p.R > 0) || !(p.T > 0)) return LBM_EINVAL;
+  if (!std::isfinite(p.sigma)) return LBM_EINVAL;
+  return LBM_OK;
+}
+
+double host_psi2(const EosConst& k, double rho) { return (pressure(k, rho) - rho / 3.0) * k.two_over_G; }
+
+// Host equilibrium, Eq. (2) with c_s^2 = 1/3.
+void host_feq(double rho, double ux, double uy, double* f) {
+  const double usq = ux * ux + uy * uy;
+  for (int a = 0; a < 9; ++a) {
+    const double eu = kEXh[a] * ux + kEYh[a] * uy;
+    f[a] = kWh[a] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+  }
+}
+
+// Fill the device-side constants of one lattice.
+RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64_t off, int run) {
+  RunDev d{};
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.pitch = pitch_of(p.nx);
+  d.eos = p.eos;
+  d.plane = (int64_t)d.pitch * p.ny;
+  d.off = off;
+  d.RT = k.RT;
+  d.c1 = k.c1;
+  d.c2 = k.c2;
+  d.two_over_G = k.two_over_G;
+  d.mG = -p.G;
+  d.inv_tau = 1.0 / p.tau;
+  switch (p.scheme) {
+    case LBM_SCHEME_SHANCHEN:  // Eqs. (9)-(10): u_eq = u + tau F/rho, no forcing term
+      d.c_eq = p.tau;
+      d.c_f = 0.0;
+      d.sig = 0.0;
+      d.Be = d.Ce = 0.0;
+      break;
+    case LBM_SCHEME_EDM:  // Eq. (11) = Eq. (16): B_e = C_e = 1, velocity u + F/(2 rho)
+      d.c_eq = 0.0;
+      d.c_f = 0.5;
+      d.sig = 0.0;
+      d.Be = d.Ce = 1.0;
+      break;
+    default:  // Eq. (31): u_eq = v, B_e = C_e = 1 - 1/(2 tau), v' = v + sigma F/((tau - 1/2) psi^2)
+      d.c_eq = 0.5;
+      d.c_f = 0.5;
+      d.sig = p.sigma / (p.tau - 0.5);
+      d.Be = d.Ce = 1.0 - 0.5 / p.tau;
+      break;
+  }
+  d.rho_ref = rho_ref;
+  d.run = run;
+  return d;
+}
+
+// Encode FP64 populations f[a][y][x] into the pre-streamed storage buffer:
+// buf[a][y][x] holds f*_a(x, y), and the kernel's pull reads it at node
+// (x + e_a, y + e_a); so buf[a][y][x] = f[a][y + ey][x + ex] (periodic).
+template <typename S>
+void encode_buffer(const lbm_params& p, double rref, const double* f, std::vector<char>& out) {
+  const int pitch = pitch_of(p.nx);
+  const size_t plane = (size_t)pitch * p.ny, n = (size_t)p.nx * p.ny;
+  out.assign(9 * plane * sizeof(S), 0);
+  S* b = reinterpret_cast<S*>(out.data());
+  for (int a = 0; a < 9; ++a)
+    for (int y = 0; y < p.ny; ++y) {
+      const int ys = (y + kEYh[a] + p.ny) % p.ny;
+      for (int x = 0; x < p.nx; ++x) {
+        const int xs = (x + kEXh[a] + p.nx) % p.nx;
+        const double v = f[a * n + (size_t)ys * p.nx + xs];
+        if constexpr (std::is_same<S, double>::value)
+          b[a * plane + (size_t)y * pitch + x] = v;
+        else if constexpr (std::is_same<S, float>::value)
+          b[a * plane + (size_t)y * pitch + x] = (float)(v - kWh[a] * rref);
+        else  // RNE to FP32, then RNE to FP16
+          b[a * plane + (size_t)y * pitch + x] = __float2half_rn((float)(v - kWh[a] * rref));
+      }
+    }
+}
+
+template <typename S>
+void decode_buffer(const lbm_params& p, double rref, const char* raw, double* f) {
+  const int pitch = pitch_of(p.nx);
+  const size_t plane = (size_t)pitch * p.ny, n = (size_t)p.nx * p.ny;
+  const S* b = reinterpret_cast<const S*>(raw);
+  for (int a = 0; a < 9; ++a)
+    for (int y = 0; y < p.ny; ++y) {
+      const int ys = (y - kEYh[a] + p.ny) % p.ny;
+      for (int x = 0; x < p.nx; ++x) {
+        const int xs = (x - kEXh[a] + p.nx) % p.nx;
+        const S v = b[a * plane + (size_t)ys * pitch + xs];
+        double d;
+        if constexpr (std::is_same<S, double>::value) {
+          d = v;
+        } else {
+          volatile double wr = kWh[a] * rref;  // keep the two roundings separate
+          if constexpr (std::is_same<S, float>::value)
+            d = (double)v + wr;
+          else
+            d = (double)__half2float(v) + wr;
+        }
+        f[a * n + (size_t)y * p.nx + x] = d;
+      }
+    }
+}
+
+void encode_any(int prec, const lbm_params& p, double rref, const double* f, std::vector<char>& o) {
+  if (prec == LBM_PREC_F64) encode_buffer<double>(p, rref, f, o);
+  else if (prec == LBM_PREC_F32DEV) encode_buffer<float>(p, rref, f, o);
+  else encode_buffer<__half>(p, rref, f, o);
+}
+void decode_any(int prec, const lbm_params& p, double rref, const char* raw, double* f) {
+  if (prec == LBM_PREC_F64) decode_buffer<double>(p, rref, raw, f);
+  else if (prec == LBM_PREC_F32DEV) decode_buffer<float>(p, rref, raw, f);
+  else decode_buffer<__half>(p, rref, raw, f);
+}
+
+// ---- launches ---------------------------------------------------------------
+
+template <typename S, int NW>
+hipError_t launch_step_t(const void* src, void* dst, const RunDev& d, int L,
+                         const unsigned long long* base, unsigned long long local,
+                         unsigned long long* flag, hipStream_t st) {
+  const int SW = 64 * NW;
+  const int nstrips = (d.nx + SW - 1) / SW, nchunks = (d.ny + L - 1) / L;
+  hipLaunchKernelGGL((k_step<S, NW>), dim3(nstrips * nchunks), dim3(SW), 0, st,
+                     static_cast<const S*>(src), static_cast<S*>(dst), d, L, nstrips, base, local,
+                     flag);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_step_s(int nw, const void* src, void* dst, const RunDev& d, int L,
+                         const unsigned long long* base, unsigned long long local,
+                         unsigned long long* flag, hipStream_t st) {
+  if (nw == 1) return launch_step_t<S, 1>(src, dst, d, L, base, local, flag, st);
+  if (nw == 2) return launch_step_t<S, 2>(src, dst, d, L, base, local, flag, st);
+  return launch_step_t<S, 4>(src, dst, d, L, base, local, flag, st);
+}
+
+hipError_t launch_step(int prec, int nw, const void* src, void* dst, const RunDev& d, int L,
+                       const unsigned long long* base, unsigned long long local,
+                       unsigned long long* flag, hipStream_t st) {
+  if (prec == LBM_PREC_F64) return launch_step_s<double>(nw, src, dst, d, L, base, local, flag, st);
+  if (prec == LBM_PREC_F32DEV) return launch_step_s<float>(nw, src, dst, d, L, base, local, flag, st);
+  return launch_step_s<__half>(nw, src, dst, d, L, base, local, flag, st);
+}
+
+template <typename S, int NW>
+hipError_t launch_batch_t(const void* src, void* dst, const RunDev* runs, const Item* items,
+                          int nitems, int grid, const unsigned long long* base,
+                          unsigned long long local, unsigned long long* flags, hipStream_t st) {
+  hipLaunchKernelGGL((k_batch_step<S, NW>), dim3(grid), dim3(64 * NW), 0, st,
+                     static_cast<const S*>(src), static_cast<S*>(dst), runs, items, nitems, base,
+                     local, flags);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_batch_s(int nw, const void* src, void* dst, const RunDev* runs,
+                          const Item* items, int nitems, int grid, const unsigned long long* base,
+                          unsigned long long local, unsigned long long* flags, hipStream_t st) {
+  if (nw == 1) return launch_batch_t<S, 1>(src, dst, runs, items, nitems, grid, base, local, flags, st);
+  if (nw == 2) return launch_batch_t<S, 2>(src, dst, runs, items, nitems, grid, base, local, flags, st);
+  return launch_batch_t<S, 4>(src, dst, runs, items, nitems, grid, base, local, flags, st);
+}
+
+hipError_t launch_batch(int prec, int nw, const void* src, void* dst, const RunDev* runs,
+                        const Item* items, int nitems, int grid, const unsigned long long* base,
+                        unsigned long long local, unsigned long long* flags, hipStream_t st) {
+  if (prec == LBM_PREC_F64)
+    return launch_batch_s<double>(nw, src, dst, runs, items, nitems, grid, base, local, flags, st);
+  if (prec == LBM_PREC_F32DEV)
+    return launch_batch_s<float>(nw, src, dst, runs, items, nitems, grid, base, local, flags, st);
+  return launch_batch_s<__half>(nw, src, dst, runs, items, nitems, grid, base, local, flags, st);
+}
+
+// Blocks per CU the batch kernel can keep resident, for the persistent grid.
+int batch_grid(int prec, int nw, int nitems) {
+  int dev = 0, ncu = 256, occ = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  const void* fn = nullptr;
+#define PICK(S)                                                      \
+  fn = nw == 1 ? (const void*)k_batch_step<S, 1>                     \
+               : nw == 2 ? (const void*)k_batch_step<S, 2> : (const void*)k_batch_step<S, 4>
+  if (prec == LBM_PREC_F64) { PICK(double); }
+  else if (prec == LBM_PREC_F32DEV) { PICK(float); }
+  else { PICK(__half); }
+#undef PICK
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64 * nw, 0) != hipSuccess || occ < 1)
+    occ = 1;
+  int g = ncu * occ;
+  g = std::min(g, (nitems + 7) / 8 * 8);
+  g = std::max(8, g / 8 * 8);
+  return g;
+}
+
+template <typename S>
+hipError_t launch_moments_s(const void* src, const RunDev& d, double* rho, double* vx, double* vy,
+                            double* p, double* psi, hipStream_t st) {
+  dim3 blk(64), grd((d.nx + 63) / 64, d.ny);
+  hipLaunchKernelGGL(k_moments1<S>, grd, blk, 0, st, static_cast<const S*>(src), d, rho, vx, vy, psi);
+  hipLaunchKernelGGL(k_moments2, grd, blk, 0, st, d, (const double*)psi, (const double*)rho, vx, vy, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int prec, const void* src, const RunDev& d, double* rho, double* vx,
+                          double* vy, double* p, double* psi, hipStream_t st) {
+  if (prec == LBM_PREC_F64) return launch_moments_s<double>(src, d, rho, vx, vy, p, psi, st);
+  if (prec == LBM_PREC_F32DEV) return launch_moments_s<float>(src, d, rho, vx, vy, p, psi, st);
+  return launch_moments_s<__half>(src, d, rho, vx, vy, p, psi, st);
+}
+
+hipError_t launch_mass(int prec, const void* src, const RunDev& d, long long* pi, double* pd,
+                       hipStream_t st) {
+  if (prec == LBM_PREC_F64)
+    hipLaunchKernelGGL(k_mass<double>, dim3(kMassBlocks), dim3(256), 0, st, (const double*)src, d, pi, pd);
+  else if (prec == LBM_PREC_F32DEV)
+    hipLaunchKernelGGL(k_mass<float>, dim3(kMassBlocks), dim3(256), 0, st, (const float*)src, d, pi, pd);
+  else
+    hipLaunchKernelGGL(k_mass<__half>, dim3(kMassBlocks), dim3(256), 0, st, (const __half*)src, d, pi, pd);
+  return hipGetLastError();
+}
+
+// ---- tile heuristics and tuning cache -----------------------------------------
+
+void default_tile(int nx, int ny, int* nw, int* L) {
+  // enough work-groups to fill 256 CUs several times over
+  *nw = nx >= 1024 ? 4 : nx >= 256 ? 2 : 1;
+  const int SW = 64 * *nw;
+  const int64_t strips = (nx + SW - 1) / SW;
+  int l = 64;
+  while (l > 4 && strips * ((ny + l - 1) / l) < 2048) l /= 2;
+  *L = std::min(l, std::max(1, ny));
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+struct lbm_ctx {
+  lbm_params p;
+  EosConst k;
+  RunDev d;
+  int esize;
+  size_t pop_bytes;
+  char* ws;
+  size_t ws_bytes;
+  void* buf[2];
+  int cur;
+  double* aux;  // 5 planes of nx*ny doubles: rho, vx, vy, p, psi
+  long long* part_i;
+  double* part_d;
+  unsigned long long* flag;
+  unsigned long long* ctr;
+  hipStream_t st;
+  int64_t step;
+  int nw, L;
+  int graph_k;
+  hipGraphExec_t gexec[2];
+  int gnw, gL;
+};
+
+namespace {
+
+size_t ctx_layout(const lbm_params& p, size_t* pop, size_t* aux, size_t* parts, size_t* misc) {
+  const size_t es = esize_of(p.precision);
+  *pop = align_up(9 * (size_t)pitch_of(p.nx) * p.ny * es);
+  *aux = align_up(5 * (size_t)p.nx * p.ny * sizeof(double));
+  *parts = align_up(kMassBlocks * (sizeof(long long) + sizeof(double)));
+  *misc = align_up(2 * sizeof(unsigned long long));
+  return 2 * *pop + *aux + *parts + *misc;
+}
+
+void drop_graphs(lbm_ctx* c) {
+  for (int i = 0; i < 2; ++i)
+    if (c->gexec[i]) {
+      (void)hipGraphExecDestroy(c->gexec[i]);
+      c->gexec[i] = nullptr;
+    }
+}
+
+int upload_state(lbm_ctx* c, const std::vector<char>& raw, int64_t step) {
+  drop_graphs(c);
+  HIPCHK(hipMemcpyAsync(c->buf[0], raw.data(), raw.size(), hipMemcpyHostToDevice, c->st));
+  c->cur = 0;
+  c->step = step;
+  hipLaunchKernelGGL(k_counter_set, dim3(1), dim3(1), 0, c->st, c->flag, kNoDiv);
+  hipLaunchKernelGGL(k_counter_set, dim3(1), dim3(1), 0, c->st, c->ctr, (unsigned long long)step);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->st));
+  return LBM_OK;
+}
+
+int capture_graph(lbm_ctx* c, int parity) {
+  hipGraph_t g;
+  HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < c->graph_k && e == hipSuccess; ++i) {
+    const int s = (parity + i) & 1;
+    e = launch_step(c->p.precision, c->nw, c->buf[s], c->buf[s ^ 1], c->d, c->L, c->ctr,
+                    (unsigned long long)i, c->flag, c->st);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_counter_add, dim3(1), dim3(1), 0, c->st, c->ctr,
+                       (unsigned long long)c->graph_k);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipStreamEndCapture(c->st, &g);
+  if (e != hipSuccess || e2 != hipSuccess) return LBM_EHIP;
+  e = hipGraphInstantiate(&c->gexec[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->gexec[parity] = nullptr;
+    return LBM_EHIP;
+  }
+  c->gnw = c->nw;
+  c->gL = c->L;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_strerror(int s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_EPSI: return "density outside the equation-of-state range (2(p - rho/3)/G <= 0)";
+    case LBM_EDIVERGED: return "the run diverged";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ENOSPACE: return "workspace too small";
+    case LBM_ENOTSUP: return "not supported";
+    default: return "unknown error";
+  }
+}
+
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
+  if (!p || !bytes) return LBM_EINVAL;
+  int st = validate(*p);
+  if (st != LBM_OK) return st;
+  size_t a, b, c2, d2;
+  *bytes = ctx_layout(*p, &a, &b, &c2, &d2);
+  return LBM_OK;
+}
+
+int lbm_init(const lbm_params* p, const double* rho0, const double* ux0, const double* uy0,
+             void* ws, size_t ws_bytes, void* stream, lbm_ctx** out) {
+  if (!p || !rho0 || !ws || !out) return LBM_EINVAL;
+  *out = nullptr;
+  int st = validate(*p);
+  if (st != LBM_OK) return st;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return LBM_EINVAL;
+  size_t pop, aux, parts, misc;
+  const size_t need = ctx_layout(*p, &pop, &aux, &parts, &misc);
+  if (ws_bytes < need) return LBM_ENOSPACE;
+  EosConst k;
+  st = eos_constants(*p, &k);
+  if (st != LBM_OK) return st;
+  const size_t n = (size_t)p->nx * p->ny;
+  double mean = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    if (!(rho0[i] > 0) || !(host_psi2(k, rho0[i]) > 0)) return LBM_EPSI;
+    mean += rho0[i];
+  }
+  mean /= (double)n;
+  double rref = 0.0;
+  if (p->precision != LBM_PREC_F64) rref = std::isnan(p->rho_ref) ? mean : p->rho_ref;
+  std::vector<double> f(9 * n);
+  for (size_t i = 0; i < n; ++i) {
+    double fe[9];
+    host_feq(rho0[i], ux0 ? ux0[i] : 0.0, uy0 ? uy0[i] : 0.0, fe);
+    for (int a = 0; a < 9; ++a) f[a * n + i] = fe[a];
+  }
+  lbm_ctx* c = new lbm_ctx{};
+  c->p = *p;
+  c->p.rho_ref = rref;
+  c->k = k;
+  c->d = make_rundev(*p, k, rref, 0, 0);
+  c->esize = esize_of(p->precision);
+  c->pop_bytes = pop;
+  c->ws = static_cast<char*>(ws);
+  c->ws_bytes = ws_bytes;
+  c->buf[0] = c->ws;
+  c->buf[1] = c->ws + pop;
+  c->aux = reinterpret_cast<double*>(c->ws + 2 * pop);
+  c->part_i = reinterpret_cast<long long*>(c->ws + 2 * pop + aux);
+  c->part_d = reinterpret_cast<double*>(c->ws + 2 * pop + aux + kMassBlocks * sizeof(long long));
+  c->flag = reinterpret_cast<unsigned long long*>(c->ws + 2 * pop + aux + parts);
+  c->ctr = c->flag + 1;
+  c->st = static_cast<hipStream_t>(stream);
+  default_tile(p->nx, p->ny, &c->nw, &c->L);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({p->nx, p->ny, p->precision, 0});
+    if (it != g_tune.end()) {
+      c->nw = it->second.first;
+      c->L = it->second.second;
+    }
+  }
+  std::vector<char> raw;
+  encode_any(p->precision, c->p, rref, f.data(), raw);
+  st = upload_state(c, raw, 0);
+  if (st != LBM_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c || n < 0) return LBM_EINVAL;
+  int64_t done = 0;
+  if (c->graph_k > 0 && n >= c->graph_k) {
+    if (c->gnw != c->nw || c->gL != c->L) drop_graphs(c);
+    hipLaunchKernelGGL(k_counter_set, dim3(1), dim3(1), 0, c->st, c->ctr, (unsigned long long)c->step);
+    HIPCHK(hipGetLastError());
+    while (n - done >= c->graph_k) {
+      if (!c->gexec[c->cur]) {
+        int st = capture_graph(c, c->cur);
+        if (st != LBM_OK) return st;
+      }
+      HIPCHK(hipGraphLaunch(c->gexec[c->cur], c->st));
+      done += c->graph_k;  // k is even: parity unchanged
+      c->step += c->graph_k;
+    }
+  }
+  for (; done < n; ++done) {
+    const int s = c->cur;
+    HIPCHK(launch_step(c->p.precision, c->nw, c->buf[s], c->buf[s ^ 1], c->d, c->L, nullptr,
+                       (unsigned long long)c->step, c->flag, c->st));
+    c->cur ^= 1;
+    c->step += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_status(lbm_ctx* c, int64_t* step, int64_t* diverged_at) {
+  if (!c) return LBM_EINVAL;
+  unsigned long long f = 0;
+  HIPCHK(hipMemcpyAsync(&f, c->flag, sizeof f, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (step) *step = c->step;
+  if (diverged_at) *diverged_at = f == kNoDiv ? -1 : (int64_t)f;
+  return f == kNoDiv ? LBM_OK : LBM_EDIVERGED;
+}
+
+int lbm_moments_device(lbm_ctx* c, double* rho, double* vx, double* vy, double* p) {
+  if (!c || !rho || !vx || !vy || !p) return LBM_EINVAL;
+  const size_t n = (size_t)c->p.nx * c->p.ny;
+  HIPCHK(launch_moments(c->p.precision, c->buf[c->cur], c->d, rho, vx, vy, p, c->aux + 4 * n, c->st));
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, double* rho, double* vx, double* vy, double* p) {
+  if (!c) return LBM_EINVAL;
+  const size_t n = (size_t)c->p.nx * c->p.ny;
+  double* a = c->aux;
+  int st = lbm_moments_device(c, a, a + n, a + 2 * n, a + 3 * n);
+  if (st != LBM_OK) return st;
+  double* outs[4] = {rho, vx, vy, p};
+  for (int i = 0; i < 4; ++i)
+    if (outs[i]) HIPCHK(hipMemcpyAsync(outs[i], a + i * n, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return lbm_status(c, nullptr, nullptr);
+}
+
+int lbm_mass(lbm_ctx* c, int64_t* fixed, double* mass) {
+  if (!c) return LBM_EINVAL;
+  HIPCHK(launch_mass(c->p.precision, c->buf[c->cur], c->d, c->part_i, c->part_d, c->st));
+  std::vector<long long> pi(kMassBlocks);
+  std::vector<double> pd(kMassBlocks);
+  HIPCHK(hipMemcpyAsync(pi.data(), c->part_i, kMassBlocks * sizeof(long long), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(pd.data(), c->part_d, kMassBlocks * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  __int128 acc = 0;
+  double m = 0.0;
+  for (int i = 0; i < kMassBlocks; ++i) {
+    acc += pi[i];
+    m += pd[i];
+  }
+  if (fixed) {
+    fixed[0] = (int64_t)(uint64_t)(unsigned __int128)acc;
+    fixed[1] = (int64_t)(acc >> 64);
+  }
+  if (mass) *mass = m;
+  return lbm_status(c, nullptr, nullptr);
+}
+
+int lbm_get_populations(lbm_ctx* c, double* f, int64_t* step) {
+  if (!c || !f) return LBM_EINVAL;
+  std::vector<char> raw(9 * (size_t)pitch_of(c->p.nx) * c->p.ny * c->esize);
+  HIPCHK(hipMemcpyAsync(raw.data(), c->buf[c->cur], raw.size(), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  decode_any(c->p.precision, c->p, c->p.rho_ref, raw.data(), f);
+  if (step) *step = c->step;
+  return lbm_status(c, nullptr, nullptr);
+}
+
+int lbm_set_populations(lbm_ctx* c, const double* f, int64_t step) {
+  if (!c || !f || step < 0) return LBM_EINVAL;
+  std::vector<char> raw;
+  encode_any(c->p.precision, c->p, c->p.rho_ref, f, raw);
+  return upload_state(c, raw, step);
+}
+
+// Checkpoint: 64-byte header {magic, version, step, precision, nx, ny, rho_ref,
+// raw bytes} followed by the raw storage of the current buffer.
+struct CkptHeader {
+  uint64_t magic, version;
+  int64_t step;
+  int32_t precision, nx, ny, pad;
+  double rho_ref;
+  uint64_t raw_bytes;
+};
+static_assert(sizeof(CkptHeader) == 56, "header layout");
+
+int lbm_state_bytes(lbm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return LBM_EINVAL;
+  *bytes = sizeof(CkptHeader) + 9 * (size_t)pitch_of(c->p.nx) * c->p.ny * c->esize;
+  return LBM_OK;
+}
+
+int lbm_save_state(lbm_ctx* c, void* host, size_t bytes) {
+  size_t need;
+  if (!c || !host || lbm_state_bytes(c, &need) != LBM_OK || bytes < need) return LBM_EINVAL;
+  CkptHeader h{0x4C424D434B505431ull, 1, c->step, c->p.precision, c->p.nx, c->p.ny, 0,
+               c->p.rho_ref, need - sizeof(CkptHeader)};
+  std::memcpy(host, &h, sizeof h);
+  HIPCHK(hipMemcpyAsync(static_cast<char*>(host) + sizeof h, c->buf[c->cur], h.raw_bytes,
+                        hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
+  if (!c || !host || bytes < sizeof(CkptHeader)) return LBM_EINVAL;
+  CkptHeader h;
+  std::memcpy(&h, host, sizeof h);
+  size_t need;
+  lbm_state_bytes(c, &need);
+  if (h.magic != 0x4C424D434B505431ull || h.version != 1 || h.precision != c->p.precision ||
+      h.nx != c->p.nx || h.ny != c->p.ny || h.raw_bytes != need - sizeof h || bytes < need)
+    return LBM_EINVAL;
+  if (!(h.rho_ref == c->p.rho_ref)) return LBM_EINVAL;
+  std::vector<char> raw(static_cast<const char*>(host) + sizeof h,
+                        static_cast<const char*>(host) + need);
+  return upload_state(c, raw, h.step);
+}
+
+int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L) {
+  if (!c || (nw != 1 && nw != 2 && nw != 4) || L < 1 || L > LMAX) return LBM_EINVAL;
+  c->nw = nw;
+  c->L = L;
+  return LBM_OK;
+}
+
+int lbm_get_tile(lbm_ctx* c, int32_t* nw, int32_t* L) {
+  if (!c) return LBM_EINVAL;
+  if (nw) *nw = c->nw;
+  if (L) *L = c->L;
+  return LBM_OK;
+}
+
+int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out) {
+  if (!c) return LBM_EINVAL;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bnw = c->nw, bL = c->L;
+  const int s = c->cur;
+  // every trial reads the current buffer and writes the other one, so the
+  // state is not advanced; the step index is the current one
+  for (int nw : {1, 2, 4}) {
+    if (nw > 1 && 64 * (nw / 2) >= c->p.nx) continue;
+    for (int L : {4, 8, 16, 32, 64, 128}) {
+      if (L > 2 * c->p.ny && L > 4) continue;
+      hipError_t e = hipSuccess;
+      for (int r = 0; r < 2 && e == hipSuccess; ++r)
+        e = launch_step(c->p.precision, nw, c->buf[s], c->buf[s ^ 1], c->d, L, nullptr,
+                        (unsigned long long)c->step, c->flag, c->st);
+      const int reps = 5;
+      e = e == hipSuccess ? hipEventRecord(e0, c->st) : e;
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = launch_step(c->p.precision, nw, c->buf[s], c->buf[s ^ 1], c->d, L, nullptr,
+                        (unsigned long long)c->step, c->flag, c->st);
+      e = e == hipSuccess ? hipEventRecord(e1, c->st) : e;
+      e = e == hipSuccess ? hipEventSynchronize(e1) : e;
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return LBM_EHIP;
+      }
+      if (ms < best) {
+        best = ms;
+        bnw = nw;
+        bL = L;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->nw = bnw;
+  c->L = bL;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[{c->p.nx, c->p.ny, c->p.precision, 0}] = {bnw, bL};
+  }
+  if (nw_out) *nw_out = bnw;
+  if (L_out) *L_out = bL;
+  return LBM_OK;
+}
+
+int lbm_set_graph_steps(lbm_ctx* c, int32_t k) {
+  if (!c || k < 0 || (k > 0 && (k < 2 || k % 2))) return LBM_EINVAL;
+  drop_graphs(c);
+  c->graph_k = k;
+  return LBM_OK;
+}
+
+int lbm_device_buffers(lbm_ctx* c, void** b0, void** b1, int32_t* cur) {
+  if (!c) return LBM_EINVAL;
+  if (b0) *b0 = c->buf[0];
+  if (b1) *b1 = c->buf[1];
+  if (cur) *cur = c->cur;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  (void)hipStreamSynchronize(c->st);
+  drop_graphs(c);
+  delete c;
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batch of independent lattices.
+// ============================================================================
+
+struct lbm_batch {
+  int nruns;
+  int prec, esize;
+  std::vector<lbm_params> p;
+  std::vector<EosConst> k;
+  std::vector<RunDev> d;        // host copy of the descriptor table
+  std::vector<int64_t> nodes;
+  char* ws;
+  size_t pool_bytes;
+  void* buf[2];
+  int cur;
+  RunDev* d_runs;
+  Item* d_items;
+  int nitems, items_cap;
+  unsigned long long* flags;
+  unsigned long long* ctr;
+  double* aux;
+  size_t aux_nodes;
+  hipStream_t st;
+  int64_t step;
+  int nw, L, grid;
+  int graph_k;
+  hipGraphExec_t gexec[2];
+  int gnw, gL;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t pool, runs, items, flags, aux, total;
+  int items_cap;
+  size_t aux_nodes;
+};
+
+BatchLayout batch_layout(int n, const lbm_params* p) {
+  BatchLayout L{};
+  size_t elems = 0, maxn = 0;
+  int cap = 0;
+  const size_t es = esize_of(p[0].precision);
+  for (int i = 0; i < n; ++i) {
+    elems += (9 * (size_t)pitch_of(p[i].nx) * p[i].ny + 63) / 64 * 64;
+    maxn = std::max(maxn, (size_t)p[i].nx * p[i].ny);
+    // the most items any tile shape can produce (waves = 1, rows = 1 is not offered; 4 is the minimum)
+    cap += ((p[i].nx + 63) / 64) * ((p[i].ny + 3) / 4);
+  }
+  L.pool = align_up(elems * es);
+  L.runs = align_up(n * sizeof(RunDev));
+  L.items_cap = cap;
+  L.items = align_up((size_t)cap * sizeof(Item));
+  L.flags = align_up((n + 1) * sizeof(unsigned long long));
+  L.aux_nodes = maxn;
+  L.aux = align_up(5 * maxn * sizeof(double));
+  L.total = 2 * L.pool + L.runs + L.items + L.flags + L.aux;
+  return L;
+}
+
+int batch_items(lbm_batch* b, int nw, int L) {
+  std::vector<Item> items;
+  const int SW = 64 * nw;
+  for (int r = 0; r < b->nruns; ++r)
+    for (int y0 = 0; y0 < b->p[r].ny; y0 += L)
+      for (int x0 = 0; x0 < b->p[r].nx; x0 += SW)
+        items.push_back(Item{r, x0, y0, std::min(SW, b->p[r].nx - x0), std::min(L, b->p[r].ny - y0), 0});
+  if ((int)items.size() > b->items_cap) return LBM_ENOSPACE;
+  HIPCHK(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  b->nitems = (int)items.size();
+  b->nw = nw;
+  b->L = L;
+  b->grid = batch_grid(b->prec, nw, b->nitems);
+  return LBM_OK;
+}
+
+void batch_drop_graphs(lbm_batch* b) {
+  for (int i = 0; i < 2; ++i)
+    if (b->gexec[i]) {
+      (void)hipGraphExecDestroy(b->gexec[i]);
+      b->gexec[i] = nullptr;
+    }
+}
+
+int batch_capture(lbm_batch* b, int parity) {
+  hipGraph_t g;
+  HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < b->graph_k && e == hipSuccess; ++i) {
+    const int s = (parity + i) & 1;
+    e = launch_batch(b->prec, b->nw, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+                     b->grid, b->ctr, (unsigned long long)i, b->flags, b->st);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_counter_add, dim3(1), dim3(1), 0, b->st, b->ctr, (unsigned long long)b->graph_k);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipStreamEndCapture(b->st, &g);
+  if (e != hipSuccess || e2 != hipSuccess) return LBM_EHIP;
+  e = hipGraphInstantiate(&b->gexec[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->gexec[parity] = nullptr;
+    return LBM_EHIP;
+  }
+  b->gnw = b->nw;
+  b->gL = b->L;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, size_t* bytes) {
+  if (n < 1 || !p || !bytes) return LBM_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    int st = validate(p[i]);
+    if (st != LBM_OK) return st;
+    if (p[i].precision != p[0].precision) return LBM_EINVAL;
+  }
+  *bytes = batch_layout(n, p).total;
+  return LBM_OK;
+}
+
+int lbm_batch_init(int32_t n, const lbm_params* p, const double* const* rho0, void* ws,
+                   size_t ws_bytes, void* stream, lbm_batch** out) {
+  if (n < 1 || !p || !rho0 || !ws || !out) return LBM_EINVAL;
+  *out = nullptr;
+  size_t need;
+  int st = lbm_batch_workspace_bytes(n, p, &need);
+  if (st != LBM_OK) return st;
+  if (ws_bytes < need) return LBM_ENOSPACE;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return LBM_EINVAL;
+  const BatchLayout Lay = batch_layout(n, p);
+  lbm_batch* b = new lbm_batch{};
+  b->nruns = n;
+  b->prec = p[0].precision;
+  b->esize = esize_of(b->prec);
+  b->p.assign(p, p + n);
+  b->k.resize(n);
+  b->ws = static_cast<char*>(ws);
+  b->pool_bytes = Lay.pool;
+  b->buf[0] = b->ws;
+  b->buf[1] = b->ws + Lay.pool;
+  b->d_runs = reinterpret_cast<RunDev*>(b->ws + 2 * Lay.pool);
+  b->d_items = reinterpret_cast<Item*>(b->ws + 2 * Lay.pool + Lay.runs);
+  b->items_cap = Lay.items_cap;
+  b->flags = reinterpret_cast<unsigned long long*>(b->ws + 2 * Lay.pool + Lay.runs + Lay.items);
+  b->ctr = b->flags + n;
+  b->aux = reinterpret_cast<double*>(b->ws + 2 * Lay.pool + Lay.runs + Lay.items + Lay.flags);
+  b->aux_nodes = Lay.aux_nodes;
+  b->st = static_cast<hipStream_t>(stream);
+  std::vector<char> pool(Lay.pool, 0);
+  int64_t off = 0;
+  for (int r = 0; r < n && st == LBM_OK; ++r) {
+    const lbm_params& q = p[r];
+    st = eos_constants(q, &b->k[r]);
+    if (st != LBM_OK) break;
+    const size_t nn = (size_t)q.nx * q.ny;
+    double mean = 0;
+    for (size_t i = 0; i < nn; ++i) {
+      if (!(rho0[r][i] > 0) || !(host_psi2(b->k[r], rho0[r][i]) > 0)) st = LBM_EPSI;
+      mean += rho0[r][i];
+    }
+    if (st != LBM_OK) break;
+    mean /= (double)nn;
+    const double rref = b->prec == LBM_PREC_F64 ? 0.0 : (std::isnan(q.rho_ref) ? mean : q.rho_ref);
+    b->p[r].rho_ref = rref;
+    b->d.push_back(make_rundev(q, b->k[r], rref, off, r));
+    b->nodes.push_back((int64_t)nn);
+    std::vector<double> f(9 * nn);
+    for (size_t i = 0; i < nn; ++i) {
+      double fe[9];
+      host_feq(rho0[r][i], 0.0, 0.0, fe);
+      for (int a = 0; a < 9; ++a) f[a * nn + i] = fe[a];
+    }
+    std::vector<char> raw;
+    encode_any(b->prec, q, rref, f.data(), raw);
+    std::memcpy(pool.data() + off * b->esize, raw.data(), raw.size());
+    off += (9 * (int64_t)pitch_of(q.nx) * q.ny + 63) / 64 * 64;
+  }
+  if (st != LBM_OK) {
+    delete b;
+    return st;
+  }
+  hipError_t e = hipMemcpyAsync(b->buf[0], pool.data(), pool.size(), hipMemcpyHostToDevice, b->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_runs, b->d.data(), n * sizeof(RunDev), hipMemcpyHostToDevice, b->st);
+  std::vector<unsigned long long> fl(n + 1, kNoDiv);
+  fl[n] = 0;  // step counter
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->flags, fl.data(), fl.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, b->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+  if (e != hipSuccess) {
+    delete b;
+    return LBM_EHIP;
+  }
+  int nw = 1, L = 16;
+  {
+    int64_t tot = 0, maxnx = 0;
+    for (int r = 0; r < n; ++r) {
+      tot += b->nodes[r];
+      maxnx = std::max<int64_t>(maxnx, p[r].nx);
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({(int)std::min<int64_t>(tot, INT32_MAX), (int)maxnx, b->prec, n});
+    if (it != g_tune.end()) {
+      nw = it->second.first;
+      L = it->second.second;
+    }
+  }
+  st = batch_items(b, nw, L);
+  if (st != LBM_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t n) {
+  if (!b || n < 0) return LBM_EINVAL;
+  int64_t done = 0;
+  if (b->graph_k > 0 && n >= b->graph_k) {
+    if (b->gnw != b->nw || b->gL != b->L) batch_drop_graphs(b);
+    hipLaunchKernelGGL(k_counter_set, dim3(1), dim3(1), 0, b->st, b->ctr, (unsigned long long)b->step);
+    HIPCHK(hipGetLastError());
+    while (n - done >= b->graph_k) {
+      if (!b->gexec[b->cur]) {
+        int st = batch_capture(b, b->cur);
+        if (st != LBM_OK) return st;
+      }
+      HIPCHK(hipGraphLaunch(b->gexec[b->cur], b->st));
+      done += b->graph_k;
+      b->step += b->graph_k;
+    }
+  }
+  for (; done < n; ++done) {
+    const int s = b->cur;
+    HIPCHK(launch_batch(b->prec, b->nw, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+                        b->grid, nullptr, (unsigned long long)b->step, b->flags, b->st));
+    b->cur ^= 1;
+    b->step += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_set_tile(lbm_batch* b, int32_t nw, int32_t L) {
+  if (!b || (nw != 1 && nw != 2 && nw != 4) || L < 4 || L > LMAX) return LBM_EINVAL;
+  batch_drop_graphs(b);
+  return batch_items(b, nw, L);
+}
+
+int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k) {
+  if (!b || k < 0 || (k > 0 && (k < 2 || k % 2))) return LBM_EINVAL;
+  batch_drop_graphs(b);
+  b->graph_k = k;
+  return LBM_OK;
+}
+
+int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out) {
+  if (!b) return LBM_EINVAL;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bnw = b->nw, bL = b->L;
+  const int s = b->cur;
+  int maxnx = 0;
+  int64_t tot = 0;
+  for (int r = 0; r < b->nruns; ++r) {
+    maxnx = std::max(maxnx, b->p[r].nx);
+    tot += b->nodes[r];
+  }
+  for (int nw : {1, 2, 4}) {
+    if (nw > 1 && 64 * (nw / 2) >= maxnx) continue;
+    for (int L : {4, 8, 16, 32, 64}) {
+      int st = batch_items(b, nw, L);
+      if (st == LBM_ENOSPACE) continue;
+      if (st != LBM_OK) return st;
+      hipError_t e = hipSuccess;
+      for (int r = 0; r < 2 && e == hipSuccess; ++r)
+        e = launch_batch(b->prec, nw, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+                         b->grid, nullptr, (unsigned long long)b->step, b->flags, b->st);
+      e = e == hipSuccess ? hipEventRecord(e0, b->st) : e;
+      for (int r = 0; r < 5 && e == hipSuccess; ++r)
+        e = launch_batch(b->prec, nw, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+                         b->grid, nullptr, (unsigned long long)b->step, b->flags, b->st);
+      e = e == hipSuccess ? hipEventRecord(e1, b->st) : e;
+      e = e == hipSuccess ? hipEventSynchronize(e1) : e;
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) return LBM_EHIP;
+      if (ms < best) {
+        best = ms;
+        bnw = nw;
+        bL = L;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  batch_drop_graphs(b);
+  int st = batch_items(b, bnw, bL);
+  if (st != LBM_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[{(int)std::min<int64_t>(tot, INT32_MAX), maxnx, b->prec, b->nruns}] = {bnw, bL};
+  }
+  if (nw_out) *nw_out = bnw;
+  if (L_out) *L_out = bL;
+  return LBM_OK;
+}
+
+int lbm_batch_nodes(lbm_batch* b, int64_t* nodes) {
+  if (!b || !nodes) return LBM_EINVAL;
+  std::vector<unsigned long long> fl(b->nruns);
+  HIPCHK(hipMemcpyAsync(fl.data(), b->flags, b->nruns * sizeof(unsigned long long), hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  int64_t t = 0;
+  for (int r = 0; r < b->nruns; ++r)
+    if (fl[r] == kNoDiv) t += b->nodes[r];
+  *nodes = t;
+  return LBM_OK;
+}
+
+int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double* vy, double* p) {
+  if (!b || run < 0 || run >= b->nruns) return LBM_EINVAL;
+  const RunDev& d = b->d[run];
+  const size_t n = (size_t)d.nx * d.ny;
+  double* a = b->aux;
+  const char* src = static_cast<const char*>(b->buf[b->cur]) + d.off * b->esize;
+  HIPCHK(launch_moments(b->prec, src, d, a, a + n, a + 2 * n, a + 3 * n, a + 4 * n, b->st));
+  double* outs[4] = {rho, vx, vy, p};
+  for (int i = 0; i < 4; ++i)
+    if (outs[i]) HIPCHK(hipMemcpyAsync(outs[i], a + i * n, n * sizeof(double), hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  return LBM_OK;
+}
+
+int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f) {
+  if (!b || run < 0 || run >= b->nruns || !f) return LBM_EINVAL;
+  const RunDev& d = b->d[run];
+  std::vector<char> raw(9 * (size_t)d.pitch * d.ny * b->esize);
+  const char* src = static_cast<const char*>(b->buf[b->cur]) + d.off * b->esize;
+  HIPCHK(hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  decode_any(b->prec, b->p[run], d.rho_ref, raw.data(), f);
+  return LBM_OK;
+}
+
+int lbm_batch_coexistence(lbm_batch* b, double* rho_l, double* rho_g, int32_t* status,
+                          int64_t* diverged_at) {
+  if (!b) return LBM_EINVAL;
+  std::vector<unsigned long long> fl(b->nruns);
+  HIPCHK(hipMemcpyAsync(fl.data(), b->flags, b->nruns * sizeof(unsigned long long), hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  std::vector<double> rho(b->aux_nodes);
+  for (int r = 0; r < b->nruns; ++r) {
+    const bool div = fl[r] != kNoDiv;
+    if (status) status[r] = div ? LBM_EDIVERGED : LBM_OK;
+    if (diverged_at) diverged_at[r] = div ? (int64_t)fl[r] : -1;
+    double l = NAN, g = NAN;
+    if (!div) {
+      int st = lbm_batch_moments(b, r, rho.data(), nullptr, nullptr, nullptr);
+      if (st != LBM_OK) return st;
+      const int nx = b->p[r].nx, ny = b->p[r].ny;
+      double sl = 0, sg = 0;
+      for (int y = 0; y < ny; ++y) {
+        sl += rho[(size_t)y * nx + nx / 2];
+        sg += rho[(size_t)y * nx];
+      }
+      l = sl / ny;
+      g = sg / ny;
+    }
+    if (rho_l) rho_l[r] = l;
+    if (rho_g) rho_g[r] = g;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_EINVAL;
+  (void)hipStreamSynchronize(b->st);
+  batch_drop_graphs(b);
+  delete b;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,195 @@
+"""Parity of the HIP fused step (through the C ABI) with the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import lbm as olbm
+from tests.gpu_common import CS, PR, droplet_rho, pair, rel_err, slab_rho
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10   # relative density tolerance, FP64 path
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_1204_4098_amd import lbm
+    assert torch.cuda.is_available()
+    lbm.lib()
+    return lbm
+
+
+def _run_both(L, gp, op, rho0, checkpoints, tile=None):
+    f = olbm.init_equilibrium(rho0)
+    lat = L.Lattice(gp, rho0)
+    lat.set_populations(f, 0)
+    if tile:
+        lat.set_tile(*tile)
+    done = 0
+    errs = []
+    for c in checkpoints:
+        assert olbm.step(op, f, c - done)[0] == 0
+        lat.step(c - done)
+        done = c
+        st, n, div = lat.status()
+        assert st == L.LBM_OK and n == c and div == -1
+        rho = lat.moments()[0]
+        ref = olbm.moments(op, f)[0]
+        errs.append(rel_err(rho, ref))
+    g, _ = lat.get_populations()
+    lat.close()
+    return errs, g, f
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.1])
+def test_config0_slab_10000_steps(L, sigma):
+    # 64 x 32, C-S at 0.8 Tc, tau = 1, improved scheme, +-1 % seeded noise, 10,000 steps
+    gp, op = pair(L, 64, 32, t=0.8, tau=1.0, scheme=2, sigma=sigma)
+    rho0 = slab_rho(64, 32, CS, 0.8)
+    errs, g, f = _run_both(L, gp, op, rho0, [1, 10, 100, 1000, 10000])
+    print("config0 sigma", sigma, "errors", errs, flush=True)
+    assert max(errs) < TOL64
+    assert np.max(np.abs(g - f)) < 1e-10 * np.max(np.abs(f))
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.5])
+def test_schemes_ragged_tiles(L, scheme, tau):
+    # ragged 67 x 29 lattice cut into 1-wave strips of 8 rows: several tiles, ragged tails
+    gp, op = pair(L, 67, 29, t=0.85, tau=tau, scheme=scheme, sigma=0.105)
+    rho0 = slab_rho(67, 29, CS, 0.85, noise=0.01, seed=7)
+    errs, _, _ = _run_both(L, gp, op, rho0, [1, 50, 300], tile=(1, 8))
+    assert max(errs) < TOL64, errs
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_peng_robinson_droplet(L, scheme):
+    gp, op = pair(L, 96, 80, t=0.8, tau=1.0, scheme=scheme, sigma=0.105, eos=PR)
+    rho0 = droplet_rho(96, 80, PR, 0.8, 20)
+    errs, _, _ = _run_both(L, gp, op, rho0, [1, 20, 200, 1000], tile=(1, 16))
+    assert max(errs) < TOL64, errs
+
+
+def test_divergence_step_matches_oracle(L):
+    # Peng-Robinson at 0.6 Tc, a sharp (W = 2) droplet: both sides leave the EOS range
+    gp, op = pair(L, 96, 80, t=0.6, tau=1.0, scheme=2, sigma=0.105, eos=PR)
+    from oracle import thermo as th
+    import synth
+    c = th.maxwell_pr(0.6)
+    rho0 = synth.droplet(96, 80, c.rho_l, c.rho_g, 20, 4.0, 0.005)
+    f = olbm.init_equilibrium(rho0)
+    st_o, d_o = olbm.step(op, f, 200)
+    lat = L.Lattice(gp, rho0)
+    lat.set_populations(olbm.init_equilibrium(rho0), 0)
+    lat.step(200)
+    st, n, d = lat.status()
+    assert st_o == olbm.EDIVERGED and st == L.LBM_EDIVERGED
+    assert abs(d - d_o) <= 2, (d, d_o)
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (5, 4), (130, 7), (64, 128)])
+def test_edge_shapes(L, shape):
+    nx, ny = shape
+    gp, op = pair(L, nx, ny, t=0.9, tau=0.9, scheme=2, sigma=0.05)
+    rng = np.random.default_rng(nx * 1000 + ny)
+    rho0 = np.ascontiguousarray(0.1 + 0.02 * rng.random((ny, nx)))
+    errs, _, _ = _run_both(L, gp, op, rho0, [1, 25])
+    assert max(errs) < TOL64, errs
+
+
+def test_tile_shapes_bitwise_identical(L):
+    gp, _ = pair(L, 200, 90, t=0.8, tau=0.7, scheme=2, sigma=0.1)
+    rho0 = slab_rho(200, 90, CS, 0.8, seed=3)
+    outs = []
+    for tile in [(1, 4), (1, 16), (2, 8), (4, 128), (4, 5), (2, 33)]:
+        lat = L.Lattice(gp, rho0)
+        lat.set_tile(*tile)
+        lat.step(37)
+        outs.append(lat.get_populations()[0])
+        lat.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_graph_replay_bitwise(L):
+    gp, _ = pair(L, 128, 64, t=0.8, tau=1.0, scheme=2, sigma=0.1)
+    rho0 = slab_rho(128, 64, CS, 0.8, seed=5)
+    a = L.Lattice(gp, rho0)
+    a.step(101)
+    fa = a.get_populations()[0]
+    b = L.Lattice(gp, rho0)
+    b.set_graph_steps(10)
+    b.step(3)        # eager, odd parity
+    b.step(40)       # graphs of 10 from the odd buffer
+    b.step(58)       # graphs again, plus an eager tail
+    st, n, div = b.status()
+    assert n == 101 and st == L.LBM_OK
+    assert np.array_equal(b.get_populations()[0], fa)
+    a.close(); b.close()
+
+
+def test_moments_match_oracle(L):
+    gp, op = pair(L, 48, 40, t=0.75, tau=0.8, scheme=1)
+    rho0 = droplet_rho(48, 40, CS, 0.75, 10)
+    f = olbm.init_equilibrium(rho0)
+    olbm.step(op, f, 30)
+    lat = L.Lattice(gp, rho0)
+    lat.set_populations(f, 30)
+    r, vx, vy, p = lat.moments()
+    R, VX, VY, P = olbm.moments(op, f)
+    assert rel_err(r, R) < 1e-14
+    assert np.max(np.abs(vx - VX)) < 1e-15 and np.max(np.abs(vy - VY)) < 1e-15
+    assert np.max(np.abs(p - P)) < 1e-15
+
+
+def test_mass_fixed_point_bit_exact(L):
+    gp, op = pair(L, 70, 33, t=0.8, tau=1.0, scheme=2, sigma=0.1)
+    rho0 = slab_rho(70, 33, CS, 0.8, seed=9)
+    f = olbm.init_equilibrium(rho0)
+    lat = L.Lattice(gp, rho0)
+    lat.set_populations(f, 0)
+    m_gpu, fx_gpu = lat.mass()
+    m_or, fx_or = olbm.mass(f)
+    assert fx_gpu == fx_or
+    lat.step(500)
+    g, _ = lat.get_populations()
+    m2, fx2 = lat.mass()
+    assert fx2 == olbm.mass(g)[1]          # identical fields -> identical integer mass
+    # conservation: rounding drift only
+    assert abs(m2 - m_or) < 500 * 70 * 33 * 4e-16
+
+
+def test_checkpoint_roundtrip_bitwise(L):
+    gp, _ = pair(L, 96, 48, t=0.8, tau=0.9, scheme=2, sigma=0.1)
+    rho0 = slab_rho(96, 48, CS, 0.8, seed=13)
+    a = L.Lattice(gp, rho0)
+    a.step(60)
+    blob = a.save_state()
+    a.step(60)
+    fa = a.get_populations()[0]
+    b = L.Lattice(gp, rho0)
+    b.load_state(blob)
+    assert b.status()[1] == 60
+    b.step(60)
+    assert np.array_equal(b.get_populations()[0], fa)
+    a.close(); b.close()
+
+
+def test_divergence_is_reported(L):
+    gp, op = pair(L, 32, 16, t=0.8)
+    rho0 = slab_rho(32, 16, CS, 0.8, noise=0.0)
+    lat = L.Lattice(gp, rho0)
+    f = olbm.init_equilibrium(rho0)
+    f[4, 5, 6] = np.nan
+    lat.set_populations(f, 7)
+    lat.step(3)
+    st, n, div = lat.status()
+    assert st == L.LBM_EDIVERGED and div == 7 and n == 10
+    # the oracle agrees on where it stopped
+    assert olbm.step(op, f, 3) == (olbm.EDIVERGED, 0)
+    # an initial density outside the EOS range is refused at init
+    bad = rho0.copy()
+    bad[0, 0] = 0.99
+    with pytest.raises(L.LbmError) as e:
+        L.Lattice(gp, bad)
+    assert e.value.status == L.LBM_EPSI
