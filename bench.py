@@ -117,7 +117,7 @@ def main():
     lat = lbm.Lattice(p, rho0, device="cuda:0")
     if not args.no_tune:
         lat.tune()
-    waves, rows = lat.get_tile()
+    waves, rows, depth = lat.get_tile()
     if args.graph_steps:
         lat.set_graph_steps(args.graph_steps)
     lat.step(args.warmup)
@@ -158,7 +158,7 @@ def main():
         "vs_baseline": None,
         "dtype": PREC_NAME[args.precision],
         "data": "synthetic",
-        "config": dict(cfg, precision=PREC_NAME[args.precision], tile_waves=waves, tile_rows=rows,
+        "config": dict(cfg, precision=PREC_NAME[args.precision], tile_waves=waves, tile_rows=rows, tile_depth=depth,
                        graph_steps=args.graph_steps),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,

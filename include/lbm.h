@@ -144,16 +144,22 @@ int lbm_state_bytes(lbm_ctx* c, size_t* bytes);
 int lbm_save_state(lbm_ctx* c, void* host_buf, size_t bytes);
 int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes);
 
-/* Tiles: a work-group of 64*waves threads owns a strip of 64*waves columns and
- * marches over `rows` rows.  lbm_tune times the candidates on the current
- * state (without advancing it) and keeps the fastest; results are cached per
- * (nx, ny, precision) for the process.  waves in {1, 2, 4}, rows in [1, 128]. */
-int lbm_tune(lbm_ctx* c, int32_t* waves, int32_t* rows);
-int lbm_set_tile(lbm_ctx* c, int32_t waves, int32_t rows);
-int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows);
+/* Launch shape ("tile") of the step kernel.  A work-group of 64*waves threads
+ * owns a strip of 64*waves columns (one column per thread) and marches up
+ * `rows` rows; rows = 0 selects the balanced schedule, in which a grid sized
+ * to the GPU's resident capacity splits all strip rows evenly.  `depth` (1 or
+ * 2) is how many rows of loads are in flight while a row is collided.
+ * waves in {1, 2, 4}; rows in [0, 128].  lbm_tune times the candidates on the
+ * current state without advancing it and keeps the fastest; the choice is
+ * cached per (nx, ny, precision) for the life of the process.  Every tile
+ * gives bitwise identical results. */
+int lbm_tune(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth);
+int lbm_set_tile(lbm_ctx* c, int32_t waves, int32_t rows, int32_t depth);
+int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth);
 
 /* Replay n steps through captured HIP graphs of k steps each (k even, >= 2;
- * 0 disables).  Results are bitwise identical to eager launches. */
+ * 0 disables).  Needs a non-null stream.  Results are bitwise identical to
+ * eager launches. */
 int lbm_set_graph_steps(lbm_ctx* c, int32_t k);
 
 /* Raw device addresses of the two population buffers (for timing and
@@ -182,8 +188,11 @@ int lbm_batch_coexistence(lbm_batch* b, double* rho_l, double* rho_g, int32_t* s
                           int64_t* diverged_at);
 int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double* vy, double* p);
 int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f);
-int lbm_batch_tune(lbm_batch* b, int32_t* waves, int32_t* rows);
-int lbm_batch_set_tile(lbm_batch* b, int32_t waves, int32_t rows);
+/* Tiles of the batch work list (rows = 0: one item per strip of up to 128
+ * rows), tuned over the whole batch like lbm_tune. */
+int lbm_batch_tune(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth);
+int lbm_batch_set_tile(lbm_batch* b, int32_t waves, int32_t rows, int32_t depth);
+int lbm_batch_get_tile(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth);
 int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k);
 /* Lattice updates per step summed over runs that are still active. */
 int lbm_batch_nodes(lbm_batch* b, int64_t* nodes);

@@ -171,9 +171,12 @@ __device__ __forceinline__ R mom_y(const R (&s)[9]) {
   return ((s[2] - s[4]) + (s[5] - s[7])) + (s[6] - s[8]);
 }
 
-// One tile: columns [x0, x0+ncols), rows [y0, y0+nrows).  All threads of the
-// block call it (barriers inside); ring is [4][SW+2], haloL/haloR [LMAX+2].
-template <typename S, int NW>
+// One tile: columns [x0, x0+ncols), rows [y0, y0+nrows), nrows <= LMAX.
+// All threads of the block call it (barriers inside); ring is [4][SW+2],
+// haloL/haloR [LMAX+2].  PF is the number of rows whose loads are in flight
+// while a row is collided: with PF = 2 the loads of row y+2 are issued before
+// the psi of row y+1 is evaluated and row y is collided.
+template <typename S, int NW, int PF>
 __device__ __forceinline__ void tile_step(const S* __restrict__ src, S* __restrict__ dst,
                                           const RunDev& d, int x0, int y0, int ncols, int nrows,
                                           unsigned long long step,
@@ -199,22 +202,22 @@ __device__ __forceinline__ void tile_step(const S* __restrict__ src, S* __restri
     R f[9];
     pull9<S>(src, d, (i & 1) ? xr : xl, yy, f);
     const double rho = rref + double(sum9(f));
-    const double p2 = psi2_of(rho, d);
-    ((i & 1) ? haloR : haloL)[k] = sqrt(p2);
+    ((i & 1) ? haloR : haloL)[k] = sqrt(psi2_of(rho, d));
   }
-  __syncthreads();
 
-  // preload rows y0-1 (ring slot 0) and y0 (slot 1)
-  R fc[9];
+  // preload rows y0-1 (ring slot 0) and y0 (slot 1); with PF = 2 also issue row y0+1
+  R fc[9], fn[9];
   double psi2c = 0.0;
   if (act) {
     R f[9];
     pull9<S>(src, d, x, y0 == 0 ? d.ny - 1 : y0 - 1, f);
-    ring[0][tid + 1] = sqrt(psi2_of(rref + double(sum9(f)), d));
     pull9<S>(src, d, x, y0, fc);
+    if (PF == 2) pull9<S>(src, d, x, y0 + 1 == d.ny ? 0 : y0 + 1, fn);
+    ring[0][tid + 1] = sqrt(psi2_of(rref + double(sum9(f)), d));
     psi2c = psi2_of(rref + double(sum9(fc)), d);
     ring[1][tid + 1] = sqrt(psi2c);
   }
+  __syncthreads();  // the halo columns are in LDS
   if (tid == 0) {
     ring[0][0] = haloL[0];
     ring[0][ncols + 1] = haloR[0];
@@ -226,10 +229,14 @@ __device__ __forceinline__ void tile_step(const S* __restrict__ src, S* __restri
     const int y = y0 + j;
     const int yn = y + 1 == d.ny ? 0 : y + 1;
     const int sl = (j + 2) & 3;
-    R fn[9];
+    R fnn[9];
     double psi2n = 0.0;
     if (act) {
-      pull9<S>(src, d, x, yn, fn);
+      if (PF == 2) {
+        if (j + 1 < nrows) pull9<S>(src, d, x, yn + 1 == d.ny ? 0 : yn + 1, fnn);
+      } else {
+        pull9<S>(src, d, x, yn, fn);
+      }
       psi2n = psi2_of(rref + double(sum9(fn)), d);
       ring[sl][tid + 1] = sqrt(psi2n);
     }
@@ -244,13 +251,18 @@ __device__ __forceinline__ void tile_step(const S* __restrict__ src, S* __restri
       const R drho = sum9(fc);
       const double rho64 = rref + double(drho);
       bad |= !(psi2c > 0.0) || !(rho64 > 0.0);
-      collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), R(1.0 / psi2c), d);
+      const R ip2 = d.sig != 0.0 ? R(1.0 / psi2c) : R(0);
+      collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
       const int64_t o = (int64_t)y * d.pitch + x;
 #pragma unroll
       for (int a = 0; a < 9; ++a) T::st(dst + a * d.plane + o, fc[a]);
 #pragma unroll
       for (int a = 0; a < 9; ++a) fc[a] = fn[a];
       psi2c = psi2n;
+      if (PF == 2 && j + 1 < nrows) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) fn[a] = fnn[a];
+      }
     }
   }
   // divergence: one atomic per wave that saw a bad node
@@ -265,7 +277,11 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return k * q + (k < r ? k : r) + i;
 }
 
-template <typename S, int NW>
+// Single-lattice step.  L > 0: one block per (strip, L-row chunk).  L == 0:
+// balanced schedule, the strip-major row space [0, nstrips*ny) is split evenly
+// over the grid (sized to the resident capacity) and each block marches its
+// share in pieces of at most LMAX rows.
+template <typename S, int NW, int PF>
 __global__ __launch_bounds__(64 * NW) void k_step(const S* __restrict__ src, S* __restrict__ dst,
                                                   RunDev d, int L, int nstrips,
                                                   const unsigned long long* stepbase,
@@ -273,18 +289,34 @@ __global__ __launch_bounds__(64 * NW) void k_step(const S* __restrict__ src, S* 
                                                   unsigned long long* flag) {
   __shared__ double ring[4][64 * NW + 2];
   __shared__ double haloL[LMAX + 2], haloR[LMAX + 2];
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int sy = t / nstrips, sx = t - sy * nstrips;
-  const int x0 = sx * 64 * NW, y0 = sy * L;
-  const int ncols = min(64 * NW, d.nx - x0), nrows = min(L, d.ny - y0);
+  constexpr int SW = 64 * NW;
   const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
   if (*flag < step) return;  // diverged at an earlier step: the run is frozen
-  tile_step<S, NW>(src, dst, d, x0, y0, ncols, nrows, step, flag, ring, haloL, haloR);
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  if (L > 0) {
+    const int sy = t / nstrips, sx = t - sy * nstrips;
+    const int x0 = sx * SW, y0 = sy * L;
+    tile_step<S, NW, PF>(src, dst, d, x0, y0, min(SW, d.nx - x0), min(L, d.ny - y0), step, flag,
+                         ring, haloL, haloR);
+    return;
+  }
+  const int64_t total = (int64_t)nstrips * d.ny;
+  int64_t r = total * t / gridDim.x;
+  const int64_t e = total * (t + 1) / gridDim.x;
+  while (r < e) {
+    const int s = (int)(r / d.ny), y = (int)(r - (int64_t)s * d.ny);
+    int n = (int)min(e - r, (int64_t)(d.ny - y));
+    n = min(n, LMAX);
+    const int x0 = s * SW;
+    tile_step<S, NW, PF>(src, dst, d, x0, y, min(SW, d.nx - x0), n, step, flag, ring, haloL, haloR);
+    r += n;
+    __syncthreads();  // LDS is reused by the next piece
+  }
 }
 
 // Persistent batched step: blocks of XCD k walk the k-th contiguous eighth of
 // the work list.  Grid must be a multiple of 8.
-template <typename S, int NW>
+template <typename S, int NW, int PF>
 __global__ __launch_bounds__(64 * NW) void k_batch_step(const S* __restrict__ src,
                                                         S* __restrict__ dst,
                                                         const RunDev* __restrict__ runs,
@@ -301,8 +333,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step(const S* __restrict__ sr
     const Item it = items[i];
     const RunDev d = runs[it.run];
     if (flags[it.run] < step) continue;
-    tile_step<S, NW>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
-                     &flags[it.run], ring, haloL, haloR);
+    tile_step<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
+                         &flags[it.run], ring, haloL, haloR);
     __syncthreads();  // LDS is reused by the next item
   }
 }

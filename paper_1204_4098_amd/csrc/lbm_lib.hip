@@ -32,9 +32,26 @@ constexpr unsigned long long kNoDiv = ~0ull;
     if ((x) != hipSuccess) return LBM_EHIP; \
   } while (0)
 
+// Launch shape of the step kernels: waves per block (strip of 64*nw columns),
+// rows per block (0 = balanced schedule over the resident grid) and the row
+// prefetch depth (1 or 2).
+struct Tile {
+  int nw, L, pf;
+};
+
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int esize_of(int prec) { return prec == LBM_PREC_F64 ? 8 : prec == LBM_PREC_F32DEV ? 4 : 2; }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+
+#ifndef LBM_PLANE_PAD_BYTES
+#define LBM_PLANE_PAD_BYTES 0
+#endif
+// Elements between consecutive direction planes: ny rows of pitch elements,
+// plus an optional pad that moves the nine planes off a common power-of-two
+// stride (so concurrent streams do not fall on the same memory channels).
+int64_t plane_of(int nx, int ny, int esize) {
+  return (int64_t)pitch_of(nx) * ny + LBM_PLANE_PAD_BYTES / esize;
+}
 
 int validate(const lbm_params& p) {
   if (p.nx < 3 || p.ny < 3) return LBM_EINVAL;
@@ -67,7 +84,7 @@ RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64
   d.ny = p.ny;
   d.pitch = pitch_of(p.nx);
   d.eos = p.eos;
-  d.plane = (int64_t)d.pitch * p.ny;
+  d.plane = plane_of(p.nx, p.ny, esize_of(p.precision));
   d.off = off;
   d.RT = k.RT;
   d.c1 = k.c1;
@@ -106,7 +123,7 @@ RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64
 template <typename S>
 void encode_buffer(const lbm_params& p, double rref, const double* f, std::vector<char>& out) {
   const int pitch = pitch_of(p.nx);
-  const size_t plane = (size_t)pitch * p.ny, n = (size_t)p.nx * p.ny;
+  const size_t plane = plane_of(p.nx, p.ny, sizeof(S)), n = (size_t)p.nx * p.ny;
   out.assign(9 * plane * sizeof(S), 0);
   S* b = reinterpret_cast<S*>(out.data());
   for (int a = 0; a < 9; ++a)
@@ -128,7 +145,7 @@ void encode_buffer(const lbm_params& p, double rref, const double* f, std::vecto
 template <typename S>
 void decode_buffer(const lbm_params& p, double rref, const char* raw, double* f) {
   const int pitch = pitch_of(p.nx);
-  const size_t plane = (size_t)pitch * p.ny, n = (size_t)p.nx * p.ny;
+  const size_t plane = plane_of(p.nx, p.ny, sizeof(S)), n = (size_t)p.nx * p.ny;
   const S* b = reinterpret_cast<const S*>(raw);
   for (int a = 0; a < 9; ++a)
     for (int y = 0; y < p.ny; ++y) {
@@ -164,85 +181,99 @@ void decode_any(int prec, const lbm_params& p, double rref, const char* raw, dou
 
 // ---- launches ---------------------------------------------------------------
 
-template <typename S, int NW>
+// Resident blocks per CU times the CU count for one kernel (cached per kernel).
+int resident_blocks(const void* fn, int threads) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int dev = 0, ncu = 256, occ = 1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, 0) != hipSuccess || occ < 1)
+    occ = 1;
+  return cache[fn] = ncu * occ;
+}
+
+template <typename S, int NW, int PF>
 hipError_t launch_step_t(const void* src, void* dst, const RunDev& d, int L,
                          const unsigned long long* base, unsigned long long local,
                          unsigned long long* flag, hipStream_t st) {
   const int SW = 64 * NW;
-  const int nstrips = (d.nx + SW - 1) / SW, nchunks = (d.ny + L - 1) / L;
-  hipLaunchKernelGGL((k_step<S, NW>), dim3(nstrips * nchunks), dim3(SW), 0, st,
-                     static_cast<const S*>(src), static_cast<S*>(dst), d, L, nstrips, base, local,
-                     flag);
+  const int nstrips = (d.nx + SW - 1) / SW;
+  int grid;
+  if (L > 0) {
+    grid = nstrips * ((d.ny + L - 1) / L);
+  } else {  // balanced: resident capacity, at least 8 rows per block
+    const int64_t rows = (int64_t)nstrips * d.ny;
+    grid = resident_blocks((const void*)k_step<S, NW, PF>, SW);
+    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, rows / 8));
+  }
+  hipLaunchKernelGGL((k_step<S, NW, PF>), dim3(grid), dim3(SW), 0, st, static_cast<const S*>(src),
+                     static_cast<S*>(dst), d, L, nstrips, base, local, flag);
   return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_step_s(int nw, const void* src, void* dst, const RunDev& d, int L,
+hipError_t launch_step_s(const Tile& t, const void* src, void* dst, const RunDev& d,
                          const unsigned long long* base, unsigned long long local,
                          unsigned long long* flag, hipStream_t st) {
-  if (nw == 1) return launch_step_t<S, 1>(src, dst, d, L, base, local, flag, st);
-  if (nw == 2) return launch_step_t<S, 2>(src, dst, d, L, base, local, flag, st);
-  return launch_step_t<S, 4>(src, dst, d, L, base, local, flag, st);
+  switch (t.nw * 10 + t.pf) {
+    case 11: return launch_step_t<S, 1, 1>(src, dst, d, t.L, base, local, flag, st);
+    case 12: return launch_step_t<S, 1, 2>(src, dst, d, t.L, base, local, flag, st);
+    case 21: return launch_step_t<S, 2, 1>(src, dst, d, t.L, base, local, flag, st);
+    case 22: return launch_step_t<S, 2, 2>(src, dst, d, t.L, base, local, flag, st);
+    case 41: return launch_step_t<S, 4, 1>(src, dst, d, t.L, base, local, flag, st);
+    default: return launch_step_t<S, 4, 2>(src, dst, d, t.L, base, local, flag, st);
+  }
 }
 
-hipError_t launch_step(int prec, int nw, const void* src, void* dst, const RunDev& d, int L,
+hipError_t launch_step(int prec, const Tile& t, const void* src, void* dst, const RunDev& d,
                        const unsigned long long* base, unsigned long long local,
                        unsigned long long* flag, hipStream_t st) {
-  if (prec == LBM_PREC_F64) return launch_step_s<double>(nw, src, dst, d, L, base, local, flag, st);
-  if (prec == LBM_PREC_F32DEV) return launch_step_s<float>(nw, src, dst, d, L, base, local, flag, st);
-  return launch_step_s<__half>(nw, src, dst, d, L, base, local, flag, st);
+  if (prec == LBM_PREC_F64) return launch_step_s<double>(t, src, dst, d, base, local, flag, st);
+  if (prec == LBM_PREC_F32DEV) return launch_step_s<float>(t, src, dst, d, base, local, flag, st);
+  return launch_step_s<__half>(t, src, dst, d, base, local, flag, st);
 }
 
-template <typename S, int NW>
+template <typename S, int NW, int PF>
 hipError_t launch_batch_t(const void* src, void* dst, const RunDev* runs, const Item* items,
-                          int nitems, int grid, const unsigned long long* base,
-                          unsigned long long local, unsigned long long* flags, hipStream_t st) {
-  hipLaunchKernelGGL((k_batch_step<S, NW>), dim3(grid), dim3(64 * NW), 0, st,
+                          int nitems, const unsigned long long* base, unsigned long long local,
+                          unsigned long long* flags, hipStream_t st) {
+  int g = resident_blocks((const void*)k_batch_step<S, NW, PF>, 64 * NW);
+  g = std::min(g, (nitems + 7) / 8 * 8);
+  g = std::max(8, g / 8 * 8);
+  hipLaunchKernelGGL((k_batch_step<S, NW, PF>), dim3(g), dim3(64 * NW), 0, st,
                      static_cast<const S*>(src), static_cast<S*>(dst), runs, items, nitems, base,
                      local, flags);
   return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_batch_s(int nw, const void* src, void* dst, const RunDev* runs,
-                          const Item* items, int nitems, int grid, const unsigned long long* base,
+hipError_t launch_batch_s(const Tile& t, const void* src, void* dst, const RunDev* runs,
+                          const Item* items, int nitems, const unsigned long long* base,
                           unsigned long long local, unsigned long long* flags, hipStream_t st) {
-  if (nw == 1) return launch_batch_t<S, 1>(src, dst, runs, items, nitems, grid, base, local, flags, st);
-  if (nw == 2) return launch_batch_t<S, 2>(src, dst, runs, items, nitems, grid, base, local, flags, st);
-  return launch_batch_t<S, 4>(src, dst, runs, items, nitems, grid, base, local, flags, st);
+  switch (t.nw * 10 + t.pf) {
+    case 11: return launch_batch_t<S, 1, 1>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 12: return launch_batch_t<S, 1, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 21: return launch_batch_t<S, 2, 1>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 22: return launch_batch_t<S, 2, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 41: return launch_batch_t<S, 4, 1>(src, dst, runs, items, nitems, base, local, flags, st);
+    default: return launch_batch_t<S, 4, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+  }
 }
 
-hipError_t launch_batch(int prec, int nw, const void* src, void* dst, const RunDev* runs,
-                        const Item* items, int nitems, int grid, const unsigned long long* base,
+hipError_t launch_batch(int prec, const Tile& t, const void* src, void* dst, const RunDev* runs,
+                        const Item* items, int nitems, const unsigned long long* base,
                         unsigned long long local, unsigned long long* flags, hipStream_t st) {
   if (prec == LBM_PREC_F64)
-    return launch_batch_s<double>(nw, src, dst, runs, items, nitems, grid, base, local, flags, st);
+    return launch_batch_s<double>(t, src, dst, runs, items, nitems, base, local, flags, st);
   if (prec == LBM_PREC_F32DEV)
-    return launch_batch_s<float>(nw, src, dst, runs, items, nitems, grid, base, local, flags, st);
-  return launch_batch_s<__half>(nw, src, dst, runs, items, nitems, grid, base, local, flags, st);
-}
-
-// Blocks per CU the batch kernel can keep resident, for the persistent grid.
-int batch_grid(int prec, int nw, int nitems) {
-  int dev = 0, ncu = 256, occ = 1;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
-  }
-  const void* fn = nullptr;
-#define PICK(S)                                                      \
-  fn = nw == 1 ? (const void*)k_batch_step<S, 1>                     \
-               : nw == 2 ? (const void*)k_batch_step<S, 2> : (const void*)k_batch_step<S, 4>
-  if (prec == LBM_PREC_F64) { PICK(double); }
-  else if (prec == LBM_PREC_F32DEV) { PICK(float); }
-  else { PICK(__half); }
-#undef PICK
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64 * nw, 0) != hipSuccess || occ < 1)
-    occ = 1;
-  int g = ncu * occ;
-  g = std::min(g, (nitems + 7) / 8 * 8);
-  g = std::max(8, g / 8 * 8);
-  return g;
+    return launch_batch_s<float>(t, src, dst, runs, items, nitems, base, local, flags, st);
+  return launch_batch_s<__half>(t, src, dst, runs, items, nitems, base, local, flags, st);
 }
 
 template <typename S>
@@ -274,18 +305,20 @@ hipError_t launch_mass(int prec, const void* src, const RunDev& d, long long* pi
 
 // ---- tile heuristics and tuning cache -----------------------------------------
 
-void default_tile(int nx, int ny, int* nw, int* L) {
-  // enough work-groups to fill 256 CUs several times over
-  *nw = nx >= 1024 ? 4 : nx >= 256 ? 2 : 1;
-  const int SW = 64 * *nw;
-  const int64_t strips = (nx + SW - 1) / SW;
-  int l = 64;
-  while (l > 4 && strips * ((ny + l - 1) / l) < 2048) l /= 2;
-  *L = std::min(l, std::max(1, ny));
+Tile default_tile(int nx, int ny) {
+  Tile t{nx >= 1024 ? 4 : nx >= 256 ? 2 : 1, 0, 2};
+  const int SW = 64 * t.nw;
+  const int64_t rows = (int64_t)((nx + SW - 1) / SW) * ny;
+  if (rows < 8 * 1024) {  // small lattices: short chunks give more blocks
+    int l = 64;
+    while (l > 4 && ((nx + SW - 1) / SW) * ((ny + l - 1) / l) < 1024) l /= 2;
+    t.L = std::min(l, std::max(1, ny));
+  }
+  return t;
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;
+std::map<std::tuple<int, int, int, int>, Tile> g_tune;
 
 }  // namespace
 }  // namespace lbm
@@ -297,7 +330,7 @@ struct lbm_ctx {
   EosConst k;
   RunDev d;
   int esize;
-  size_t pop_bytes;
+  size_t pop_bytes, raw_bytes;
   char* ws;
   size_t ws_bytes;
   void* buf[2];
@@ -309,21 +342,31 @@ struct lbm_ctx {
   unsigned long long* ctr;
   hipStream_t st;
   int64_t step;
-  int nw, L;
+  Tile tile;
   int graph_k;
   hipGraphExec_t gexec[2];
-  int gnw, gL;
+  Tile gtile;
 };
 
 namespace {
 
+size_t raw_bytes_of(const lbm_params& p) {
+  const int es = esize_of(p.precision);
+  return 9 * (size_t)plane_of(p.nx, p.ny, es) * es;
+}
+
 size_t ctx_layout(const lbm_params& p, size_t* pop, size_t* aux, size_t* parts, size_t* misc) {
-  const size_t es = esize_of(p.precision);
-  *pop = align_up(9 * (size_t)pitch_of(p.nx) * p.ny * es);
+  *pop = align_up(raw_bytes_of(p));
   *aux = align_up(5 * (size_t)p.nx * p.ny * sizeof(double));
   *parts = align_up(kMassBlocks * (sizeof(long long) + sizeof(double)));
   *misc = align_up(2 * sizeof(unsigned long long));
   return 2 * *pop + *aux + *parts + *misc;
+}
+
+bool same_tile(const Tile& a, const Tile& b) { return a.nw == b.nw && a.L == b.L && a.pf == b.pf; }
+
+bool valid_tile(int nw, int L, int pf) {
+  return (nw == 1 || nw == 2 || nw == 4) && L >= 0 && L <= LMAX && (pf == 1 || pf == 2);
 }
 
 void drop_graphs(lbm_ctx* c) {
@@ -352,7 +395,7 @@ int capture_graph(lbm_ctx* c, int parity) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < c->graph_k && e == hipSuccess; ++i) {
     const int s = (parity + i) & 1;
-    e = launch_step(c->p.precision, c->nw, c->buf[s], c->buf[s ^ 1], c->d, c->L, c->ctr,
+    e = launch_step(c->p.precision, c->tile, c->buf[s], c->buf[s ^ 1], c->d, c->ctr,
                     (unsigned long long)i, c->flag, c->st);
   }
   if (e == hipSuccess) {
@@ -368,9 +411,31 @@ int capture_graph(lbm_ctx* c, int parity) {
     c->gexec[parity] = nullptr;
     return LBM_EHIP;
   }
-  c->gnw = c->nw;
-  c->gL = c->L;
+  c->gtile = c->tile;
   return LBM_OK;
+}
+
+// Time `reps` launches of one candidate tile (reads the current buffer, writes
+// the other, so the state does not advance).  Returns ms or a negative value.
+template <class Launch>
+float time_launches(hipStream_t st, Launch&& launch, int reps) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.f;
+  }
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = -1.f;
+  if (e == hipSuccess && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return e == hipSuccess ? ms : -1.f;
 }
 
 }  // namespace
@@ -434,6 +499,7 @@ int lbm_init(const lbm_params* p, const double* rho0, const double* ux0, const d
   c->d = make_rundev(*p, k, rref, 0, 0);
   c->esize = esize_of(p->precision);
   c->pop_bytes = pop;
+  c->raw_bytes = raw_bytes_of(*p);
   c->ws = static_cast<char*>(ws);
   c->ws_bytes = ws_bytes;
   c->buf[0] = c->ws;
@@ -444,14 +510,11 @@ int lbm_init(const lbm_params* p, const double* rho0, const double* ux0, const d
   c->flag = reinterpret_cast<unsigned long long*>(c->ws + 2 * pop + aux + parts);
   c->ctr = c->flag + 1;
   c->st = static_cast<hipStream_t>(stream);
-  default_tile(p->nx, p->ny, &c->nw, &c->L);
+  c->tile = default_tile(p->nx, p->ny);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find({p->nx, p->ny, p->precision, 0});
-    if (it != g_tune.end()) {
-      c->nw = it->second.first;
-      c->L = it->second.second;
-    }
+    if (it != g_tune.end()) c->tile = it->second;
   }
   std::vector<char> raw;
   encode_any(p->precision, c->p, rref, f.data(), raw);
@@ -468,7 +531,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
   if (!c || n < 0) return LBM_EINVAL;
   int64_t done = 0;
   if (c->graph_k > 0 && n >= c->graph_k) {
-    if (c->gnw != c->nw || c->gL != c->L) drop_graphs(c);
+    if (!same_tile(c->gtile, c->tile)) drop_graphs(c);
     hipLaunchKernelGGL(k_counter_set, dim3(1), dim3(1), 0, c->st, c->ctr, (unsigned long long)c->step);
     HIPCHK(hipGetLastError());
     while (n - done >= c->graph_k) {
@@ -483,7 +546,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
   }
   for (; done < n; ++done) {
     const int s = c->cur;
-    HIPCHK(launch_step(c->p.precision, c->nw, c->buf[s], c->buf[s ^ 1], c->d, c->L, nullptr,
+    HIPCHK(launch_step(c->p.precision, c->tile, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
                        (unsigned long long)c->step, c->flag, c->st));
     c->cur ^= 1;
     c->step += 1;
@@ -545,7 +608,7 @@ int lbm_mass(lbm_ctx* c, int64_t* fixed, double* mass) {
 
 int lbm_get_populations(lbm_ctx* c, double* f, int64_t* step) {
   if (!c || !f) return LBM_EINVAL;
-  std::vector<char> raw(9 * (size_t)pitch_of(c->p.nx) * c->p.ny * c->esize);
+  std::vector<char> raw(c->raw_bytes);
   HIPCHK(hipMemcpyAsync(raw.data(), c->buf[c->cur], raw.size(), hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   decode_any(c->p.precision, c->p, c->p.rho_ref, raw.data(), f);
@@ -560,8 +623,8 @@ int lbm_set_populations(lbm_ctx* c, const double* f, int64_t step) {
   return upload_state(c, raw, step);
 }
 
-// Checkpoint: 64-byte header {magic, version, step, precision, nx, ny, rho_ref,
-// raw bytes} followed by the raw storage of the current buffer.
+// Checkpoint: a header {magic, version, step, precision, nx, ny, rho_ref, raw
+// bytes} followed by the raw storage of the current buffer.
 struct CkptHeader {
   uint64_t magic, version;
   int64_t step;
@@ -570,20 +633,19 @@ struct CkptHeader {
   uint64_t raw_bytes;
 };
 static_assert(sizeof(CkptHeader) == 56, "header layout");
+constexpr uint64_t kCkptMagic = 0x4C424D434B505431ull;
 
 int lbm_state_bytes(lbm_ctx* c, size_t* bytes) {
   if (!c || !bytes) return LBM_EINVAL;
-  *bytes = sizeof(CkptHeader) + 9 * (size_t)pitch_of(c->p.nx) * c->p.ny * c->esize;
+  *bytes = sizeof(CkptHeader) + c->raw_bytes;
   return LBM_OK;
 }
 
 int lbm_save_state(lbm_ctx* c, void* host, size_t bytes) {
-  size_t need;
-  if (!c || !host || lbm_state_bytes(c, &need) != LBM_OK || bytes < need) return LBM_EINVAL;
-  CkptHeader h{0x4C424D434B505431ull, 1, c->step, c->p.precision, c->p.nx, c->p.ny, 0,
-               c->p.rho_ref, need - sizeof(CkptHeader)};
+  if (!c || !host || bytes < sizeof(CkptHeader) + c->raw_bytes) return LBM_EINVAL;
+  CkptHeader h{kCkptMagic, 1, c->step, c->p.precision, c->p.nx, c->p.ny, 0, c->p.rho_ref, c->raw_bytes};
   std::memcpy(host, &h, sizeof h);
-  HIPCHK(hipMemcpyAsync(static_cast<char*>(host) + sizeof h, c->buf[c->cur], h.raw_bytes,
+  HIPCHK(hipMemcpyAsync(static_cast<char*>(host) + sizeof h, c->buf[c->cur], c->raw_bytes,
                         hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   return LBM_OK;
@@ -593,85 +655,70 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
   if (!c || !host || bytes < sizeof(CkptHeader)) return LBM_EINVAL;
   CkptHeader h;
   std::memcpy(&h, host, sizeof h);
-  size_t need;
-  lbm_state_bytes(c, &need);
-  if (h.magic != 0x4C424D434B505431ull || h.version != 1 || h.precision != c->p.precision ||
-      h.nx != c->p.nx || h.ny != c->p.ny || h.raw_bytes != need - sizeof h || bytes < need)
+  if (h.magic != kCkptMagic || h.version != 1 || h.precision != c->p.precision || h.nx != c->p.nx ||
+      h.ny != c->p.ny || h.raw_bytes != c->raw_bytes || bytes < sizeof h + c->raw_bytes ||
+      !(h.rho_ref == c->p.rho_ref) || h.step < 0)
     return LBM_EINVAL;
-  if (!(h.rho_ref == c->p.rho_ref)) return LBM_EINVAL;
   std::vector<char> raw(static_cast<const char*>(host) + sizeof h,
-                        static_cast<const char*>(host) + need);
+                        static_cast<const char*>(host) + sizeof h + c->raw_bytes);
   return upload_state(c, raw, h.step);
 }
 
-int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L) {
-  if (!c || (nw != 1 && nw != 2 && nw != 4) || L < 1 || L > LMAX) return LBM_EINVAL;
-  c->nw = nw;
-  c->L = L;
+int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth) {
+  if (!c || !valid_tile(nw, L, depth)) return LBM_EINVAL;
+  c->tile = Tile{nw, L, depth};
   return LBM_OK;
 }
 
-int lbm_get_tile(lbm_ctx* c, int32_t* nw, int32_t* L) {
+int lbm_get_tile(lbm_ctx* c, int32_t* nw, int32_t* L, int32_t* depth) {
   if (!c) return LBM_EINVAL;
-  if (nw) *nw = c->nw;
-  if (L) *L = c->L;
+  if (nw) *nw = c->tile.nw;
+  if (L) *L = c->tile.L;
+  if (depth) *depth = c->tile.pf;
   return LBM_OK;
 }
 
-int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out) {
+int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out) {
   if (!c) return LBM_EINVAL;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
-  int bnw = c->nw, bL = c->L;
+  Tile bt = c->tile;
   const int s = c->cur;
-  // every trial reads the current buffer and writes the other one, so the
-  // state is not advanced; the step index is the current one
+  const int64_t nodes = (int64_t)c->p.nx * c->p.ny;
+  const int reps = nodes >= (1 << 22) ? 3 : 10;
   for (int nw : {1, 2, 4}) {
     if (nw > 1 && 64 * (nw / 2) >= c->p.nx) continue;
-    for (int L : {4, 8, 16, 32, 64, 128}) {
-      if (L > 2 * c->p.ny && L > 4) continue;
-      hipError_t e = hipSuccess;
-      for (int r = 0; r < 2 && e == hipSuccess; ++r)
-        e = launch_step(c->p.precision, nw, c->buf[s], c->buf[s ^ 1], c->d, L, nullptr,
-                        (unsigned long long)c->step, c->flag, c->st);
-      const int reps = 5;
-      e = e == hipSuccess ? hipEventRecord(e0, c->st) : e;
-      for (int r = 0; r < reps && e == hipSuccess; ++r)
-        e = launch_step(c->p.precision, nw, c->buf[s], c->buf[s ^ 1], c->d, L, nullptr,
-                        (unsigned long long)c->step, c->flag, c->st);
-      e = e == hipSuccess ? hipEventRecord(e1, c->st) : e;
-      e = e == hipSuccess ? hipEventSynchronize(e1) : e;
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return LBM_EHIP;
+    for (int pf : {1, 2})
+      for (int L : {0, 4, 8, 16, 32, 64, 128}) {
+        if (L > 2 * c->p.ny) continue;
+        const Tile t{nw, L, pf};
+        const float ms = time_launches(
+            c->st,
+            [&] {
+              return launch_step(c->p.precision, t, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
+                                 (unsigned long long)c->step, c->flag, c->st);
+            },
+            reps);
+        if (ms < 0) return LBM_EHIP;
+        if (ms < best) {
+          best = ms;
+          bt = t;
+        }
       }
-      if (ms < best) {
-        best = ms;
-        bnw = nw;
-        bL = L;
-      }
-    }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  c->nw = bnw;
-  c->L = bL;
+  c->tile = bt;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[{c->p.nx, c->p.ny, c->p.precision, 0}] = {bnw, bL};
+    g_tune[{c->p.nx, c->p.ny, c->p.precision, 0}] = bt;
   }
-  if (nw_out) *nw_out = bnw;
-  if (L_out) *L_out = bL;
+  if (nw_out) *nw_out = bt.nw;
+  if (L_out) *L_out = bt.L;
+  if (depth_out) *depth_out = bt.pf;
   return LBM_OK;
 }
 
 int lbm_set_graph_steps(lbm_ctx* c, int32_t k) {
   if (!c || k < 0 || (k > 0 && (k < 2 || k % 2))) return LBM_EINVAL;
+  if (k > 0 && c->st == nullptr) return LBM_EINVAL;  // the null stream cannot be captured
   drop_graphs(c);
   c->graph_k = k;
   return LBM_OK;
@@ -704,7 +751,7 @@ struct lbm_batch {
   int prec, esize;
   std::vector<lbm_params> p;
   std::vector<EosConst> k;
-  std::vector<RunDev> d;        // host copy of the descriptor table
+  std::vector<RunDev> d;  // host copy of the descriptor table
   std::vector<int64_t> nodes;
   char* ws;
   size_t pool_bytes;
@@ -719,10 +766,10 @@ struct lbm_batch {
   size_t aux_nodes;
   hipStream_t st;
   int64_t step;
-  int nw, L, grid;
+  Tile tile;
   int graph_k;
   hipGraphExec_t gexec[2];
-  int gnw, gL;
+  Tile gtile;
 };
 
 namespace {
@@ -733,15 +780,19 @@ struct BatchLayout {
   size_t aux_nodes;
 };
 
+int64_t run_elems(const lbm_params& q) {
+  return (9 * plane_of(q.nx, q.ny, esize_of(q.precision)) + 63) / 64 * 64;
+}
+
 BatchLayout batch_layout(int n, const lbm_params* p) {
   BatchLayout L{};
   size_t elems = 0, maxn = 0;
   int cap = 0;
   const size_t es = esize_of(p[0].precision);
   for (int i = 0; i < n; ++i) {
-    elems += (9 * (size_t)pitch_of(p[i].nx) * p[i].ny + 63) / 64 * 64;
+    elems += run_elems(p[i]);
     maxn = std::max(maxn, (size_t)p[i].nx * p[i].ny);
-    // the most items any tile shape can produce (waves = 1, rows = 1 is not offered; 4 is the minimum)
+    // the most items any offered tile can produce (1 wave, 4 rows)
     cap += ((p[i].nx + 63) / 64) * ((p[i].ny + 3) / 4);
   }
   L.pool = align_up(elems * es);
@@ -755,20 +806,21 @@ BatchLayout batch_layout(int n, const lbm_params* p) {
   return L;
 }
 
-int batch_items(lbm_batch* b, int nw, int L) {
+// Work list: tiles of every run; L = 0 means one item per whole strip column.
+int batch_items(lbm_batch* b, const Tile& t) {
   std::vector<Item> items;
-  const int SW = 64 * nw;
-  for (int r = 0; r < b->nruns; ++r)
+  const int SW = 64 * t.nw;
+  for (int r = 0; r < b->nruns; ++r) {
+    const int L = t.L > 0 ? t.L : std::min(b->p[r].ny, LMAX);
     for (int y0 = 0; y0 < b->p[r].ny; y0 += L)
       for (int x0 = 0; x0 < b->p[r].nx; x0 += SW)
         items.push_back(Item{r, x0, y0, std::min(SW, b->p[r].nx - x0), std::min(L, b->p[r].ny - y0), 0});
+  }
   if ((int)items.size() > b->items_cap) return LBM_ENOSPACE;
   HIPCHK(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, b->st));
   HIPCHK(hipStreamSynchronize(b->st));
   b->nitems = (int)items.size();
-  b->nw = nw;
-  b->L = L;
-  b->grid = batch_grid(b->prec, nw, b->nitems);
+  b->tile = t;
   return LBM_OK;
 }
 
@@ -786,8 +838,8 @@ int batch_capture(lbm_batch* b, int parity) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < b->graph_k && e == hipSuccess; ++i) {
     const int s = (parity + i) & 1;
-    e = launch_batch(b->prec, b->nw, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
-                     b->grid, b->ctr, (unsigned long long)i, b->flags, b->st);
+    e = launch_batch(b->prec, b->tile, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+                     b->ctr, (unsigned long long)i, b->flags, b->st);
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_counter_add, dim3(1), dim3(1), 0, b->st, b->ctr, (unsigned long long)b->graph_k);
@@ -801,9 +853,18 @@ int batch_capture(lbm_batch* b, int parity) {
     b->gexec[parity] = nullptr;
     return LBM_EHIP;
   }
-  b->gnw = b->nw;
-  b->gL = b->L;
+  b->gtile = b->tile;
   return LBM_OK;
+}
+
+std::tuple<int, int, int, int> batch_key(const lbm_batch* b) {
+  int64_t tot = 0;
+  int maxnx = 0;
+  for (int r = 0; r < b->nruns; ++r) {
+    tot += b->nodes[r];
+    maxnx = std::max(maxnx, b->p[r].nx);
+  }
+  return {(int)std::min<int64_t>(tot, INT32_MAX), maxnx, b->prec, b->nruns};
 }
 
 }  // namespace
@@ -830,6 +891,8 @@ int lbm_batch_init(int32_t n, const lbm_params* p, const double* const* rho0, vo
   if (st != LBM_OK) return st;
   if (ws_bytes < need) return LBM_ENOSPACE;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return LBM_EINVAL;
+  for (int r = 0; r < n; ++r)
+    if (!rho0[r]) return LBM_EINVAL;
   const BatchLayout Lay = batch_layout(n, p);
   lbm_batch* b = new lbm_batch{};
   b->nruns = n;
@@ -876,7 +939,7 @@ int lbm_batch_init(int32_t n, const lbm_params* p, const double* const* rho0, vo
     std::vector<char> raw;
     encode_any(b->prec, q, rref, f.data(), raw);
     std::memcpy(pool.data() + off * b->esize, raw.data(), raw.size());
-    off += (9 * (int64_t)pitch_of(q.nx) * q.ny + 63) / 64 * 64;
+    off += run_elems(q);
   }
   if (st != LBM_OK) {
     delete b;
@@ -894,21 +957,13 @@ int lbm_batch_init(int32_t n, const lbm_params* p, const double* const* rho0, vo
     delete b;
     return LBM_EHIP;
   }
-  int nw = 1, L = 16;
+  Tile t{1, 16, 2};
   {
-    int64_t tot = 0, maxnx = 0;
-    for (int r = 0; r < n; ++r) {
-      tot += b->nodes[r];
-      maxnx = std::max<int64_t>(maxnx, p[r].nx);
-    }
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find({(int)std::min<int64_t>(tot, INT32_MAX), (int)maxnx, b->prec, n});
-    if (it != g_tune.end()) {
-      nw = it->second.first;
-      L = it->second.second;
-    }
+    auto it = g_tune.find(batch_key(b));
+    if (it != g_tune.end()) t = it->second;
   }
-  st = batch_items(b, nw, L);
+  st = batch_items(b, t);
   if (st != LBM_OK) {
     delete b;
     return st;
@@ -921,7 +976,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
   if (!b || n < 0) return LBM_EINVAL;
   int64_t done = 0;
   if (b->graph_k > 0 && n >= b->graph_k) {
-    if (b->gnw != b->nw || b->gL != b->L) batch_drop_graphs(b);
+    if (!same_tile(b->gtile, b->tile)) batch_drop_graphs(b);
     hipLaunchKernelGGL(k_counter_set, dim3(1), dim3(1), 0, b->st, b->ctr, (unsigned long long)b->step);
     HIPCHK(hipGetLastError());
     while (n - done >= b->graph_k) {
@@ -936,78 +991,75 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
   }
   for (; done < n; ++done) {
     const int s = b->cur;
-    HIPCHK(launch_batch(b->prec, b->nw, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
-                        b->grid, nullptr, (unsigned long long)b->step, b->flags, b->st));
+    HIPCHK(launch_batch(b->prec, b->tile, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+                        nullptr, (unsigned long long)b->step, b->flags, b->st));
     b->cur ^= 1;
     b->step += 1;
   }
   return LBM_OK;
 }
 
-int lbm_batch_set_tile(lbm_batch* b, int32_t nw, int32_t L) {
-  if (!b || (nw != 1 && nw != 2 && nw != 4) || L < 4 || L > LMAX) return LBM_EINVAL;
+int lbm_batch_set_tile(lbm_batch* b, int32_t nw, int32_t L, int32_t depth) {
+  if (!b || !valid_tile(nw, L, depth) || (L > 0 && L < 4)) return LBM_EINVAL;
   batch_drop_graphs(b);
-  return batch_items(b, nw, L);
+  return batch_items(b, Tile{nw, L, depth});
+}
+
+int lbm_batch_get_tile(lbm_batch* b, int32_t* nw, int32_t* L, int32_t* depth) {
+  if (!b) return LBM_EINVAL;
+  if (nw) *nw = b->tile.nw;
+  if (L) *L = b->tile.L;
+  if (depth) *depth = b->tile.pf;
+  return LBM_OK;
 }
 
 int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k) {
   if (!b || k < 0 || (k > 0 && (k < 2 || k % 2))) return LBM_EINVAL;
+  if (k > 0 && b->st == nullptr) return LBM_EINVAL;
   batch_drop_graphs(b);
   b->graph_k = k;
   return LBM_OK;
 }
 
-int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out) {
+int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth_out) {
   if (!b) return LBM_EINVAL;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
-  int bnw = b->nw, bL = b->L;
+  Tile bt = b->tile;
   const int s = b->cur;
   int maxnx = 0;
-  int64_t tot = 0;
-  for (int r = 0; r < b->nruns; ++r) {
-    maxnx = std::max(maxnx, b->p[r].nx);
-    tot += b->nodes[r];
-  }
+  for (int r = 0; r < b->nruns; ++r) maxnx = std::max(maxnx, b->p[r].nx);
   for (int nw : {1, 2, 4}) {
     if (nw > 1 && 64 * (nw / 2) >= maxnx) continue;
-    for (int L : {4, 8, 16, 32, 64}) {
-      int st = batch_items(b, nw, L);
-      if (st == LBM_ENOSPACE) continue;
-      if (st != LBM_OK) return st;
-      hipError_t e = hipSuccess;
-      for (int r = 0; r < 2 && e == hipSuccess; ++r)
-        e = launch_batch(b->prec, nw, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
-                         b->grid, nullptr, (unsigned long long)b->step, b->flags, b->st);
-      e = e == hipSuccess ? hipEventRecord(e0, b->st) : e;
-      for (int r = 0; r < 5 && e == hipSuccess; ++r)
-        e = launch_batch(b->prec, nw, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
-                         b->grid, nullptr, (unsigned long long)b->step, b->flags, b->st);
-      e = e == hipSuccess ? hipEventRecord(e1, b->st) : e;
-      e = e == hipSuccess ? hipEventSynchronize(e1) : e;
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) return LBM_EHIP;
-      if (ms < best) {
-        best = ms;
-        bnw = nw;
-        bL = L;
+    for (int pf : {1, 2})
+      for (int L : {0, 4, 8, 16, 32, 64}) {
+        const Tile t{nw, L, pf};
+        int st = batch_items(b, t);
+        if (st == LBM_ENOSPACE) continue;
+        if (st != LBM_OK) return st;
+        const float ms = time_launches(
+            b->st,
+            [&] {
+              return launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items,
+                                  b->nitems, nullptr, (unsigned long long)b->step, b->flags, b->st);
+            },
+            5);
+        if (ms < 0) return LBM_EHIP;
+        if (ms < best) {
+          best = ms;
+          bt = t;
+        }
       }
-    }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   batch_drop_graphs(b);
-  int st = batch_items(b, bnw, bL);
+  int st = batch_items(b, bt);
   if (st != LBM_OK) return st;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[{(int)std::min<int64_t>(tot, INT32_MAX), maxnx, b->prec, b->nruns}] = {bnw, bL};
+    g_tune[batch_key(b)] = bt;
   }
-  if (nw_out) *nw_out = bnw;
-  if (L_out) *L_out = bL;
+  if (nw_out) *nw_out = bt.nw;
+  if (L_out) *L_out = bt.L;
+  if (depth_out) *depth_out = bt.pf;
   return LBM_OK;
 }
 
@@ -1040,7 +1092,7 @@ int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double
 int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f) {
   if (!b || run < 0 || run >= b->nruns || !f) return LBM_EINVAL;
   const RunDev& d = b->d[run];
-  std::vector<char> raw(9 * (size_t)d.pitch * d.ny * b->esize);
+  std::vector<char> raw(raw_bytes_of(b->p[run]));
   const char* src = static_cast<const char*>(b->buf[b->cur]) + d.off * b->esize;
   HIPCHK(hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, b->st));
   HIPCHK(hipStreamSynchronize(b->st));

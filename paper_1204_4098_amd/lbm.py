@@ -61,9 +61,9 @@ _SIGS = {
     "lbm_state_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "lbm_save_state": (C.c_int, [_vp, _vp, C.c_size_t]),
     "lbm_load_state": (C.c_int, [_vp, _vp, C.c_size_t]),
-    "lbm_tune": (C.c_int, [_vp, _ip, _ip]),
-    "lbm_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32]),
-    "lbm_get_tile": (C.c_int, [_vp, _ip, _ip]),
+    "lbm_tune": (C.c_int, [_vp, _ip, _ip, _ip]),
+    "lbm_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
+    "lbm_get_tile": (C.c_int, [_vp, _ip, _ip, _ip]),
     "lbm_set_graph_steps": (C.c_int, [_vp, C.c_int32]),
     "lbm_device_buffers": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), _ip]),
     "lbm_destroy": (C.c_int, [_vp]),
@@ -73,8 +73,9 @@ _SIGS = {
     "lbm_batch_coexistence": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_batch_moments": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "lbm_batch_get_populations": (C.c_int, [_vp, C.c_int32, _vp]),
-    "lbm_batch_tune": (C.c_int, [_vp, _ip, _ip]),
-    "lbm_batch_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "lbm_batch_tune": (C.c_int, [_vp, _ip, _ip, _ip]),
+    "lbm_batch_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
+    "lbm_batch_get_tile": (C.c_int, [_vp, _ip, _ip, _ip]),
     "lbm_batch_set_graph_steps": (C.c_int, [_vp, C.c_int32]),
     "lbm_batch_nodes": (C.c_int, [_vp, _lp]),
     "lbm_batch_destroy": (C.c_int, [_vp]),
@@ -235,17 +236,17 @@ class Lattice:
 
     # -- launch shape
     def tune(self):
-        w, r = C.c_int32(), C.c_int32()
-        _check(lib().lbm_tune(self.ctx, C.byref(w), C.byref(r)), "lbm_tune")
-        return w.value, r.value
+        w, r, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbm_tune(self.ctx, C.byref(w), C.byref(r), C.byref(d)), "lbm_tune")
+        return w.value, r.value, d.value
 
-    def set_tile(self, waves: int, rows: int):
-        _check(lib().lbm_set_tile(self.ctx, int(waves), int(rows)), "lbm_set_tile")
+    def set_tile(self, waves: int, rows: int, depth: int = 2):
+        _check(lib().lbm_set_tile(self.ctx, int(waves), int(rows), int(depth)), "lbm_set_tile")
 
     def get_tile(self):
-        w, r = C.c_int32(), C.c_int32()
-        _check(lib().lbm_get_tile(self.ctx, C.byref(w), C.byref(r)), "lbm_get_tile")
-        return w.value, r.value
+        w, r, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbm_get_tile(self.ctx, C.byref(w), C.byref(r), C.byref(d)), "lbm_get_tile")
+        return w.value, r.value, d.value
 
     def set_graph_steps(self, k: int):
         _check(lib().lbm_set_graph_steps(self.ctx, int(k)), "lbm_set_graph_steps")
@@ -316,12 +317,17 @@ class Batch:
         return f
 
     def tune(self):
-        w, r = C.c_int32(), C.c_int32()
-        _check(lib().lbm_batch_tune(self.b, C.byref(w), C.byref(r)), "lbm_batch_tune")
-        return w.value, r.value
+        w, r, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbm_batch_tune(self.b, C.byref(w), C.byref(r), C.byref(d)), "lbm_batch_tune")
+        return w.value, r.value, d.value
 
-    def set_tile(self, waves: int, rows: int):
-        _check(lib().lbm_batch_set_tile(self.b, int(waves), int(rows)), "lbm_batch_set_tile")
+    def set_tile(self, waves: int, rows: int, depth: int = 2):
+        _check(lib().lbm_batch_set_tile(self.b, int(waves), int(rows), int(depth)), "lbm_batch_set_tile")
+
+    def get_tile(self):
+        w, r, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbm_batch_get_tile(self.b, C.byref(w), C.byref(r), C.byref(d)), "lbm_batch_get_tile")
+        return w.value, r.value, d.value
 
     def set_graph_steps(self, k: int):
         _check(lib().lbm_batch_set_graph_steps(self.b, int(k)), "lbm_batch_set_graph_steps")

@@ -101,7 +101,8 @@ def test_tile_shapes_bitwise_identical(L):
     gp, _ = pair(L, 200, 90, t=0.8, tau=0.7, scheme=2, sigma=0.1)
     rho0 = slab_rho(200, 90, CS, 0.8, seed=3)
     outs = []
-    for tile in [(1, 4), (1, 16), (2, 8), (4, 128), (4, 5), (2, 33)]:
+    for tile in [(1, 4, 1), (1, 16, 2), (2, 8, 1), (4, 128, 2), (4, 5, 2), (2, 33, 1), (1, 0, 2),
+                 (4, 0, 1), (2, 0, 2)]:
         lat = L.Lattice(gp, rho0)
         lat.set_tile(*tile)
         lat.step(37)
