@@ -158,3 +158,31 @@ def sweep_runs(count: int, seed: int = BASE_SEED, lx=(64, 512, 32), ly=(16, 64, 
             sigma=float(sigma_range[0] + (sigma_range[1] - sigma_range[0]) * u[4]),
         ))
     return runs
+
+
+# --- sigma-surrogate network: seeded initial weights -------------------------
+
+MLP_SHAPES = [("W1", (64, 3)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+              ("W3", (2, 64)), ("b3", (2,))]
+MLP_NPARAMS = sum(int(np.prod(s)) for _, s in MLP_SHAPES)     # 4546
+
+
+def mlp_init(seed: int = BASE_SEED) -> np.ndarray:
+    """Initial parameters of the 3-64-64-2 network as one float32 vector.
+
+    Weights ~ U(-1/sqrt(fan_in), +1/sqrt(fan_in)) from the counter-based
+    generator, biases 0.  Layout: W1 (64x3, row = output unit), b1, W2 (64x64),
+    b2, W3 (2x64), b3.
+    """
+    parts = []
+    k = 0
+    for name, shape in MLP_SHAPES:
+        n = int(np.prod(shape))
+        if name.startswith("W"):
+            bound = 1.0 / np.sqrt(shape[1])
+            u = uniform(seed, 5000, np.arange(k, k + n, dtype=np.uint64))
+            parts.append(((2.0 * u - 1.0) * bound).astype(np.float32))
+        else:
+            parts.append(np.zeros(n, dtype=np.float32))
+        k += n
+    return np.concatenate(parts)
