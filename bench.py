@@ -9,6 +9,12 @@ algorithmic HBM traffic (9 populations read + 9 written per node) against the
 the kernel runs on.  `cpu_baseline` times the plain FP64 oracle on the host
 on a bounded sample of the same workload.
 
+Further legs (same line): `batched` -- 256 uneven flat-interface runs in one
+persistent launch per step, FP32 deviations versus the same runs through the
+plain FP64 path, with the FP32-vs-FP64 coexistence-density error; `precision`
+-- the default lattice with FP32 and FP16 deviation storage; `droplet1024` --
+the 1024 x 1024 Peng-Robinson droplet.
+
 Workloads (all synthetic, seeded):
   droplet1024   1024 x 1024 periodic, Peng-Robinson (a=2/49, b=2/21, R=1,
                 omega=0.344), one centred droplet of radius 128 (tanh, width 2,
@@ -29,8 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_LUP = {0: 144, 1: 72, 2: 36}     # 2 x 9 populations x storage bytes
-PREC_NAME = {0: "f64", 1: "f32dev", 2: "f16dev"}
+BYTES_PER_LUP = {0: 144, 1: 72, 2: 36, 3: 72}     # 2 x 9 populations x storage bytes
+PREC_NAME = {0: "f64", 1: "f32dev", 2: "f16dev", 3: "f32dev_f64arith"}
 
 
 def workload(name: str, t_over_tc: float | None):
@@ -96,12 +102,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="droplet1024", choices=["droplet1024", "droplets4096"])
-    ap.add_argument("--precision", type=int, default=0, choices=[0, 1, 2])
+    ap.add_argument("--workload", default="droplets4096", choices=["droplet1024", "droplets4096"])
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 1, 2, 3])
     ap.add_argument("--t-over-tc", type=float, default=None)
     ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="batched,precision,droplet1024",
+                    help="comma-separated extra legs, or 'none'")
+    ap.add_argument("--batch-steps", type=int, default=30000,
+                    help="steps of the batched FP32-vs-FP64 coexistence comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -113,62 +123,188 @@ def main():
     from paper_1204_4098_amd import lbm
 
     nx, ny, rho0, kw, cfg = workload(args.workload, args.t_over_tc)
-    p = lbm.params(nx, ny, precision=args.precision, **kw)
-    lat = lbm.Lattice(p, rho0, device="cuda:0")
-    if not args.no_tune:
-        lat.tune()
-    waves, rows, depth = lat.get_tile()
-    if args.graph_steps:
-        lat.set_graph_steps(args.graph_steps)
-    lat.step(args.warmup)
-    st, _, div = lat.status()
-    if st != lbm.LBM_OK:
-        raise SystemExit(f"bench: the run diverged at step {div} during warm-up; timing would be invalid")
-
-    stream = lat.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    lat.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st, nsteps, div = lat.status()
-    if st != lbm.LBM_OK:
-        raise SystemExit(f"bench: the run diverged at step {div} inside the timed region; "
-                         "the measurement is invalid")
-    wall = t1 - t0
-    kern_ms = e0.elapsed_time(e1) / args.steps        # average per step launch on the stream
-    nodes = nx * ny
-    mlups = nodes * args.steps / wall / 1e6
+    res = time_lattice(lbm, torch, nx, ny, rho0, kw, args.precision, args.steps, args.warmup,
+                       args.graph_steps, not args.no_tune)
     bpl = BYTES_PER_LUP[args.precision]
-    achieved = bpl * nodes / (kern_ms * 1e-3) / 1e9
+    achieved = bpl * nx * ny / (res["kernel_ms"] * 1e-3) / 1e9
     out = {
         "metric": "D2Q9 MLUPS & %HBM roofline; batched FP32 vs plain FP64 at <=1e-4 density err",
-        "value": round(mlups, 1),
+        "value": round(res["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "ms_per_step": round(res["wall_s"] / args.steps * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": PREC_NAME[args.precision],
         "data": "synthetic",
-        "config": dict(cfg, precision=PREC_NAME[args.precision], tile_waves=waves, tile_rows=rows, tile_depth=depth,
+        "config": dict(cfg, precision=PREC_NAME[args.precision], tile=res["tile"],
                        graph_steps=args.graph_steps),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic_for(args.workload, args.precision, res["tile"]),
                      "kernel": "k_step", "bytes_per_lup": bpl,
-                     "kernel_avg_us": round(kern_ms * 1e3, 2)},
+                     "kernel_avg_us": round(res["kernel_ms"] * 1e3, 2)},
     }
-    lat.close()
+    log(f"main leg done: {out['value']} MLUPS, {out['roofline']['frac']:.3f} of HBM peak")
+    legs = [] if args.legs == "none" else args.legs.split(",")
+    if "precision" in legs:
+        out["precision"] = {}
+        for prec in (1, 2, 3):
+            r = time_lattice(lbm, torch, nx, ny, rho0, kw, prec, args.steps, args.warmup,
+                             args.graph_steps, not args.no_tune)
+            gbs = BYTES_PER_LUP[prec] * nx * ny / (r["kernel_ms"] * 1e-3) / 1e9
+            out["precision"][PREC_NAME[prec]] = {"mlups": round(r["mlups"], 1), "tile": r["tile"],
+                                                 "achieved_gbs": round(gbs, 1),
+                                                 "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                                 "bytes_per_lup": BYTES_PER_LUP[prec]}
+            log(f"precision {PREC_NAME[prec]}: {r['mlups']:.0f} MLUPS")
+    if "droplet1024" in legs and args.workload != "droplet1024":
+        d = {}
+        for t in (0.6, 0.8):
+            nx1, ny1, rho1, kw1, cfg1 = workload("droplet1024", t)
+            for prec in (0, 1):
+                try:
+                    r = time_lattice(lbm, torch, nx1, ny1, rho1, kw1, prec, 2000, 50, args.graph_steps,
+                                     not args.no_tune)
+                    d[f"t{t}_{PREC_NAME[prec]}"] = {"mlups": round(r["mlups"], 1), "tile": r["tile"]}
+                except Diverged as e:
+                    d[f"t{t}_{PREC_NAME[prec]}"] = {"diverged_at_step": e.step}
+        log(f"droplet1024 leg: {d}")
+        out["droplet1024"] = dict(d, note="1024^2 Peng-Robinson droplet r=128, tau=1, improved "
+                                          "sigma=0.105; at 0.6 Tc the run leaves the EOS range")
+    if "batched" in legs:
+        out["batched"] = batched_leg(lbm, torch, args.batch_steps, args.graph_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(kw, rho0)
     print(json.dumps(out), flush=True)
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+class Diverged(RuntimeError):
+    def __init__(self, step):
+        super().__init__(f"diverged at step {step}")
+        self.step = step
+
+
+def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_steps, tune):
+    """Warm up, then time `steps` steps between a device sync on both sides."""
+    p = lbm.params(nx, ny, precision=precision, **kw)
+    lat = lbm.Lattice(p, rho0, device="cuda:0")
+    if tune:
+        lat.tune()
+    tile = list(lat.get_tile())
+    if graph_steps:
+        lat.set_graph_steps(graph_steps)
+    lat.step(warmup)
+    st, _, div = lat.status()
+    if st != lbm.LBM_OK:
+        lat.close()
+        raise Diverged(div)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st, _, div = lat.status()
+    lat.close()
+    if st != lbm.LBM_OK:
+        raise Diverged(div)
+    return {"mlups": nx * ny * steps / wall / 1e6, "wall_s": wall,
+            "kernel_ms": e0.elapsed_time(e1) / steps, "tile": tile}
+
+
+def traffic_for(workload, precision, tile):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    workload, precision and tile (FETCH_SIZE and WRITE_SIZE scaled by a plain
+    copy's readings), or None when no summary matches."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        table = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    key = f"{workload}/{PREC_NAME[precision]}/{tile[0]}x{tile[1]}x{tile[2]}"
+    e = table.get("entries", {}).get(key)
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def batched_leg(lbm, torch, batch_steps, graph_steps):
+    """256 uneven flat-interface runs (Lx in 64..512 step 32, Ly in 16..64 step 16,
+    T/Tc in [0.5, 0.95], tau in [0.6, 1.5], sigma in [0, 0.2], C-S): one persistent
+    launch per step, in FP32 deviations (FP32 and FP64 collision arithmetic) and in
+    FP64, against the same runs through the plain FP64 path (one context per run,
+    run after run).  Coexistence densities are averaged over the last 4000 steps."""
+    import numpy as np
+
+    import synth
+    from paper_1204_4098_amd import surrogate
+    runs = synth.sweep_runs(256)
+    nodes = sum(r["nx"] * r["ny"] for r in runs)
+    res = {"runs": 256, "nodes": nodes, "coexistence_steps": batch_steps}
+    for prec in (1, 3, 0):
+        ps, rhos = surrogate.slab_runs(runs, prec)
+        b = lbm.Batch(ps, rhos)
+        b.tune()
+        if graph_steps:
+            b.set_graph_steps(100)
+        b.step(200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(2000)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[f"{PREC_NAME[prec]}_batched_mlups"] = round(nodes * 2000 / wall / 1e6, 1)
+        res[f"{PREC_NAME[prec]}_batched_tile"] = list(b.get_tile())
+        b.close()
+        log(f"batched {PREC_NAME[prec]}: {res[f'{PREC_NAME[prec]}_batched_mlups']} MLUPS")
+    # the plain FP64 path: one lattice context per run, each stepped in turn
+    ps, rhos = surrogate.slab_runs(runs, 0)
+    lats = [lbm.Lattice(p, r) for p, r in zip(ps, rhos)]
+    for lat in lats:
+        lat.set_graph_steps(20)
+        lat.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.step(200)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for lat in lats:
+        lat.close()
+    res["f64_plain_mlups"] = round(nodes * 200 / wall / 1e6, 1)
+    log(f"plain FP64 path: {res['f64_plain_mlups']} MLUPS")
+    for prec in (1, 3):
+        res[f"ratio_{PREC_NAME[prec]}_batched_vs_f64_plain"] = round(
+            res[f"{PREC_NAME[prec]}_batched_mlups"] / res["f64_plain_mlups"], 2)
+        res[f"ratio_{PREC_NAME[prec]}_batched_vs_f64_batched"] = round(
+            res[f"{PREC_NAME[prec]}_batched_mlups"] / res["f64_batched_mlups"], 2)
+    # coexistence densities after batch_steps, FP32 storage vs FP64
+    out = {prec: surrogate.run_batch(runs, batch_steps, prec, window=4000, samples=20) for prec in (0, 1, 3)}
+    ref = out[0]
+    res["diverged_f64"] = int(np.sum(ref["status"] != 0))
+    for prec in (1, 3):
+        o = out[prec]
+        ok = (ref["status"] == 0) & (o["status"] == 0)
+        err = np.maximum(np.abs(o["rho_l"][ok] / ref["rho_l"][ok] - 1), np.abs(o["rho_g"][ok] / ref["rho_g"][ok] - 1))
+        settled = ref["spread"][ok] < 1e-3
+        n = PREC_NAME[prec]
+        res[f"{n}_diverged"] = int(np.sum(o["status"] != 0))
+        res[f"{n}_coex_rel_err_median"] = float(np.median(err))
+        res[f"{n}_runs_within_1e-4"] = f"{int(np.sum(err <= 1e-4))}/{int(ok.sum())}"
+        res[f"{n}_settled_runs_within_1e-4"] = f"{int(np.sum(err[settled] <= 1e-4))}/{int(settled.sum())}"
+        res[f"{n}_coex_rel_err_p90"] = float(np.quantile(err, 0.9))
+        log(f"coexistence {n}: median {res[f'{n}_coex_rel_err_median']:.2e}, within 1e-4 "
+            f"{res[f'{n}_runs_within_1e-4']}")
+    return res
 
 
 if __name__ == "__main__":

@@ -68,8 +68,10 @@ enum {
 enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 };
 enum { LBM_SCHEME_SHANCHEN = 0, LBM_SCHEME_EDM = 1, LBM_SCHEME_IMPROVED = 2 };
 /* Storage of populations: FP64, or deviations d_a = f_a - w_a rho_ref stored
- * in FP32 / FP16 with FP32 collision arithmetic (the EOS and psi stay FP64). */
-enum { LBM_PREC_F64 = 0, LBM_PREC_F32DEV = 1, LBM_PREC_F16DEV = 2 };
+ * in FP32 / FP16 with FP32 collision arithmetic (the EOS, psi and force stay
+ * FP64), or FP32 deviations with FP64 collision arithmetic.  rho_ref = 0 stores
+ * the populations themselves. */
+enum { LBM_PREC_F64 = 0, LBM_PREC_F32DEV = 1, LBM_PREC_F16DEV = 2, LBM_PREC_F32DEV_F64 = 3 };
 
 typedef struct {
   int32_t nx, ny;    /* lattice size, periodic; 3 <= nx, ny; nx*ny < 2^31 */

@@ -344,3 +344,19 @@ def maxwell_pr(t_over_tc: float) -> Coexistence:
 def mechanical_cs(t_over_tc: float, eps: float) -> Coexistence:
     Tc, _ = critical_cs()
     return mechanical(cs_default(), mp.mpf(t_over_tc) * mp.mpf(Tc), eps)
+
+
+def sigma_star_cs(t_over_tc: float, tol: float = 1e-7) -> float:
+    """Theory sigma* (C-S): the eps whose Eq. (26) solution has the Maxwell vapour
+    density, mapped back with eps = 16 sigma (Sec. IV.B); secant iteration."""
+    target = maxwell_cs(t_over_tc).rho_g
+    f = lambda e: mechanical_cs(t_over_tc, float(e)).rho_g / target - 1.0
+    e0, e1 = 1.6, 1.75
+    f0, f1 = f(e0), f(e1)
+    for _ in range(30):
+        e2 = e1 - f1 * (e1 - e0) / (f1 - f0)
+        if abs(e2 - e1) < tol:
+            e1 = e2
+            break
+        e0, f0, e1, f1 = e1, f1, e2, f(e2)
+    return sigma_of_epsilon(e1)

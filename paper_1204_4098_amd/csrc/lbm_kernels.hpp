@@ -51,23 +51,32 @@ struct Item {
   int32_t run, x0, y0, ncols, nrows, pad;
 };
 
+// Storage traits: E = element type in memory, R = collision arithmetic type.
+struct f32s_f64a {};  // FP32 deviation storage with FP64 collision arithmetic
 template <typename S> struct Store;
 template <> struct Store<double> {
+  using E = double;
   using R = double;
-  static __device__ __forceinline__ R ld(const double* p) { return __builtin_nontemporal_load(p); }
-  static __device__ __forceinline__ void st(double* p, R v) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ R ld(const E* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<float> {
+  using E = float;
   using R = float;
-  static __device__ __forceinline__ R ld(const float* p) { return __builtin_nontemporal_load(p); }
-  static __device__ __forceinline__ void st(float* p, R v) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ R ld(const E* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(v, p); }
+};
+template <> struct Store<f32s_f64a> {
+  using E = float;
+  using R = double;
+  static __device__ __forceinline__ R ld(const E* p) { return double(__builtin_nontemporal_load(p)); }
+  static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(float(v), p); }
 };
 template <> struct Store<__half> {
+  using E = __half;
   using R = float;
-  static __device__ __forceinline__ R ld(const __half* p) {
-    return __half2float(*p);
-  }
-  static __device__ __forceinline__ void st(__half* p, R v) { *p = __float2half_rn(v); }
+  static __device__ __forceinline__ R ld(const E* p) { return __half2float(*p); }
+  static __device__ __forceinline__ void st(E* p, R v) { *p = __float2half_rn(v); }
 };
 
 __device__ constexpr int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -77,7 +86,7 @@ __device__ constexpr double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
 
 // Pull the 9 populations of node (x, y) from the post-collision field.
 template <typename S>
-__device__ __forceinline__ void pull9(const S* __restrict__ src, const RunDev& d, int x, int y,
+__device__ __forceinline__ void pull9(const typename Store<S>::E* __restrict__ src, const RunDev& d, int x, int y,
                                       typename Store<S>::R (&f)[9]) {
   const int xm = x == 0 ? d.nx - 1 : x - 1;
   const int xp = x == d.nx - 1 ? 0 : x + 1;
@@ -177,7 +186,8 @@ __device__ __forceinline__ R mom_y(const R (&s)[9]) {
 // while a row is collided: with PF = 2 the loads of row y+2 are issued before
 // the psi of row y+1 is evaluated and row y is collided.
 template <typename S, int NW, int PF>
-__device__ __forceinline__ void tile_step(const S* __restrict__ src, S* __restrict__ dst,
+__device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict__ src,
+                                          typename Store<S>::E* __restrict__ dst,
                                           const RunDev& d, int x0, int y0, int ncols, int nrows,
                                           unsigned long long step,
                                           unsigned long long* __restrict__ flag,
@@ -282,7 +292,8 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // over the grid (sized to the resident capacity) and each block marches its
 // share in pieces of at most LMAX rows.
 template <typename S, int NW, int PF>
-__global__ __launch_bounds__(64 * NW) void k_step(const S* __restrict__ src, S* __restrict__ dst,
+__global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __restrict__ src,
+                                                  typename Store<S>::E* __restrict__ dst,
                                                   RunDev d, int L, int nstrips,
                                                   const unsigned long long* stepbase,
                                                   unsigned long long steplocal,
@@ -317,8 +328,8 @@ __global__ __launch_bounds__(64 * NW) void k_step(const S* __restrict__ src, S* 
 // Persistent batched step: blocks of XCD k walk the k-th contiguous eighth of
 // the work list.  Grid must be a multiple of 8.
 template <typename S, int NW, int PF>
-__global__ __launch_bounds__(64 * NW) void k_batch_step(const S* __restrict__ src,
-                                                        S* __restrict__ dst,
+__global__ __launch_bounds__(64 * NW) void k_batch_step(const typename Store<S>::E* __restrict__ src,
+                                                        typename Store<S>::E* __restrict__ dst,
                                                         const RunDev* __restrict__ runs,
                                                         const Item* __restrict__ items, int nitems,
                                                         const unsigned long long* stepbase,
@@ -347,7 +358,7 @@ __global__ void k_counter_set(unsigned long long* ctr, unsigned long long v) { *
 
 // Pass 1: rho, u = j/rho and psi at every node (rho/ux/uy/psi planes, [y][x]).
 template <typename S>
-__global__ void k_moments1(const S* __restrict__ src, RunDev d, double* rho, double* ux,
+__global__ void k_moments1(const typename Store<S>::E* __restrict__ src, RunDev d, double* rho, double* ux,
                            double* uy, double* psi) {
   using R = typename Store<S>::R;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
@@ -386,18 +397,13 @@ __global__ void k_moments2(RunDev d, const double* __restrict__ psi, const doubl
 
 // Decode one stored population to FP64 exactly as the host decoder does:
 // f = s + (w * rho_ref), two separately rounded operations.
-template <typename S>
-__device__ __forceinline__ double decode(S v, int a, double rref) {
+__device__ __forceinline__ double decode(double v, int, double) { return v; }
+__device__ __forceinline__ double decode(float v, int a, double rref) {
 #pragma clang fp contract(off)
   const double wr = kW[a] * rref;
-  return double(typename Store<S>::R(v)) + wr;
+  return double(v) + wr;
 }
-template <>
-__device__ __forceinline__ double decode<double>(double v, int, double) {
-  return v;
-}
-template <>
-__device__ __forceinline__ double decode<__half>(__half v, int a, double rref) {
+__device__ __forceinline__ double decode(__half v, int a, double rref) {
 #pragma clang fp contract(off)
   const double wr = kW[a] * rref;
   return double(__half2float(v)) + wr;
@@ -406,7 +412,7 @@ __device__ __forceinline__ double decode<__half>(__half v, int a, double rref) {
 // Mass: per block, sum of round-to-nearest-even(rho * 2^40) (exact, int64) and
 // the FP64 sum; rho = sum_a f_a in direction order of the decoded populations.
 template <typename S>
-__global__ __launch_bounds__(256) void k_mass(const S* __restrict__ src, RunDev d,
+__global__ __launch_bounds__(256) void k_mass(const typename Store<S>::E* __restrict__ src, RunDev d,
                                               long long* part_i, double* part_d) {
   __shared__ long long si[256];
   __shared__ double sd[256];
@@ -423,7 +429,7 @@ __global__ __launch_bounds__(256) void k_mass(const S* __restrict__ src, RunDev 
                             3 * P + r0 + xp, 4 * P + rp + x,  5 * P + rm + xm,
                             6 * P + rm + xp, 7 * P + rp + xp, 8 * P + rp + xm};
     double r = 0.0;
-    for (int a = 0; a < 9; ++a) r += decode<S>(src[idx[a]], a, d.rho_ref);
+    for (int a = 0; a < 9; ++a) r += decode(src[idx[a]], a, d.rho_ref);
     acc_i += __double2ll_rn(r * 1099511627776.0);  // 2^40, exact scaling
     acc_d += r;
   }

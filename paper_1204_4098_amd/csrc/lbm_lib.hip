@@ -40,7 +40,7 @@ struct Tile {
 };
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-int esize_of(int prec) { return prec == LBM_PREC_F64 ? 8 : prec == LBM_PREC_F32DEV ? 4 : 2; }
+int esize_of(int prec) { return prec == LBM_PREC_F64 ? 8 : prec == LBM_PREC_F16DEV ? 2 : 4; }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 #ifndef LBM_PLANE_PAD_BYTES
@@ -60,7 +60,7 @@ int validate(const lbm_params& p) {
   if (!(p.G != 0.0) || !std::isfinite(p.G)) return LBM_EINVAL;
   if (p.eos != LBM_EOS_CS && p.eos != LBM_EOS_PR) return LBM_EINVAL;
   if (p.scheme < LBM_SCHEME_SHANCHEN || p.scheme > LBM_SCHEME_IMPROVED) return LBM_EINVAL;
-  if (p.precision < LBM_PREC_F64 || p.precision > LBM_PREC_F16DEV) return LBM_EINVAL;
+  if (p.precision < LBM_PREC_F64 || p.precision > LBM_PREC_F32DEV_F64) return LBM_EINVAL;
   if (!(p.a > 0) || !(p.b > 0) || !(p.R > 0) || !(p.T > 0)) return LBM_EINVAL;
   if (!std::isfinite(p.sigma)) return LBM_EINVAL;
   return LBM_OK;
@@ -170,13 +170,13 @@ void decode_buffer(const lbm_params& p, double rref, const char* raw, double* f)
 
 void encode_any(int prec, const lbm_params& p, double rref, const double* f, std::vector<char>& o) {
   if (prec == LBM_PREC_F64) encode_buffer<double>(p, rref, f, o);
-  else if (prec == LBM_PREC_F32DEV) encode_buffer<float>(p, rref, f, o);
-  else encode_buffer<__half>(p, rref, f, o);
+  else if (prec == LBM_PREC_F16DEV) encode_buffer<__half>(p, rref, f, o);
+  else encode_buffer<float>(p, rref, f, o);
 }
 void decode_any(int prec, const lbm_params& p, double rref, const char* raw, double* f) {
   if (prec == LBM_PREC_F64) decode_buffer<double>(p, rref, raw, f);
-  else if (prec == LBM_PREC_F32DEV) decode_buffer<float>(p, rref, raw, f);
-  else decode_buffer<__half>(p, rref, raw, f);
+  else if (prec == LBM_PREC_F16DEV) decode_buffer<__half>(p, rref, raw, f);
+  else decode_buffer<float>(p, rref, raw, f);
 }
 
 // ---- launches ---------------------------------------------------------------
@@ -212,8 +212,9 @@ hipError_t launch_step_t(const void* src, void* dst, const RunDev& d, int L,
     grid = resident_blocks((const void*)k_step<S, NW, PF>, SW);
     grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, rows / 8));
   }
-  hipLaunchKernelGGL((k_step<S, NW, PF>), dim3(grid), dim3(SW), 0, st, static_cast<const S*>(src),
-                     static_cast<S*>(dst), d, L, nstrips, base, local, flag);
+  using E = typename Store<S>::E;
+  hipLaunchKernelGGL((k_step<S, NW, PF>), dim3(grid), dim3(SW), 0, st, static_cast<const E*>(src),
+                     static_cast<E*>(dst), d, L, nstrips, base, local, flag);
   return hipGetLastError();
 }
 
@@ -236,6 +237,7 @@ hipError_t launch_step(int prec, const Tile& t, const void* src, void* dst, cons
                        unsigned long long* flag, hipStream_t st) {
   if (prec == LBM_PREC_F64) return launch_step_s<double>(t, src, dst, d, base, local, flag, st);
   if (prec == LBM_PREC_F32DEV) return launch_step_s<float>(t, src, dst, d, base, local, flag, st);
+  if (prec == LBM_PREC_F32DEV_F64) return launch_step_s<f32s_f64a>(t, src, dst, d, base, local, flag, st);
   return launch_step_s<__half>(t, src, dst, d, base, local, flag, st);
 }
 
@@ -246,8 +248,9 @@ hipError_t launch_batch_t(const void* src, void* dst, const RunDev* runs, const 
   int g = resident_blocks((const void*)k_batch_step<S, NW, PF>, 64 * NW);
   g = std::min(g, (nitems + 7) / 8 * 8);
   g = std::max(8, g / 8 * 8);
+  using E = typename Store<S>::E;
   hipLaunchKernelGGL((k_batch_step<S, NW, PF>), dim3(g), dim3(64 * NW), 0, st,
-                     static_cast<const S*>(src), static_cast<S*>(dst), runs, items, nitems, base,
+                     static_cast<const E*>(src), static_cast<E*>(dst), runs, items, nitems, base,
                      local, flags);
   return hipGetLastError();
 }
@@ -273,6 +276,8 @@ hipError_t launch_batch(int prec, const Tile& t, const void* src, void* dst, con
     return launch_batch_s<double>(t, src, dst, runs, items, nitems, base, local, flags, st);
   if (prec == LBM_PREC_F32DEV)
     return launch_batch_s<float>(t, src, dst, runs, items, nitems, base, local, flags, st);
+  if (prec == LBM_PREC_F32DEV_F64)
+    return launch_batch_s<f32s_f64a>(t, src, dst, runs, items, nitems, base, local, flags, st);
   return launch_batch_s<__half>(t, src, dst, runs, items, nitems, base, local, flags, st);
 }
 
@@ -280,7 +285,8 @@ template <typename S>
 hipError_t launch_moments_s(const void* src, const RunDev& d, double* rho, double* vx, double* vy,
                             double* p, double* psi, hipStream_t st) {
   dim3 blk(64), grd((d.nx + 63) / 64, d.ny);
-  hipLaunchKernelGGL(k_moments1<S>, grd, blk, 0, st, static_cast<const S*>(src), d, rho, vx, vy, psi);
+  hipLaunchKernelGGL(k_moments1<S>, grd, blk, 0, st, static_cast<const typename Store<S>::E*>(src), d, rho,
+                     vx, vy, psi);
   hipLaunchKernelGGL(k_moments2, grd, blk, 0, st, d, (const double*)psi, (const double*)rho, vx, vy, p);
   return hipGetLastError();
 }
@@ -289,6 +295,7 @@ hipError_t launch_moments(int prec, const void* src, const RunDev& d, double* rh
                           double* vy, double* p, double* psi, hipStream_t st) {
   if (prec == LBM_PREC_F64) return launch_moments_s<double>(src, d, rho, vx, vy, p, psi, st);
   if (prec == LBM_PREC_F32DEV) return launch_moments_s<float>(src, d, rho, vx, vy, p, psi, st);
+  if (prec == LBM_PREC_F32DEV_F64) return launch_moments_s<f32s_f64a>(src, d, rho, vx, vy, p, psi, st);
   return launch_moments_s<__half>(src, d, rho, vx, vy, p, psi, st);
 }
 
@@ -298,6 +305,8 @@ hipError_t launch_mass(int prec, const void* src, const RunDev& d, long long* pi
     hipLaunchKernelGGL(k_mass<double>, dim3(kMassBlocks), dim3(256), 0, st, (const double*)src, d, pi, pd);
   else if (prec == LBM_PREC_F32DEV)
     hipLaunchKernelGGL(k_mass<float>, dim3(kMassBlocks), dim3(256), 0, st, (const float*)src, d, pi, pd);
+  else if (prec == LBM_PREC_F32DEV_F64)
+    hipLaunchKernelGGL(k_mass<f32s_f64a>, dim3(kMassBlocks), dim3(256), 0, st, (const float*)src, d, pi, pd);
   else
     hipLaunchKernelGGL(k_mass<__half>, dim3(kMassBlocks), dim3(256), 0, st, (const __half*)src, d, pi, pd);
   return hipGetLastError();

@@ -6,6 +6,7 @@ the library's HIP kernels.  PyTorch holds the device workspace and batches.
 from __future__ import annotations
 
 import ctypes as C
+import math
 
 import numpy as np
 import torch
@@ -117,8 +118,10 @@ class Mlp:
         _check(lib().mlp_adam(self.ctx, g.data_ptr(), lr, beta1, beta2, eps), "mlp_adam")
         self.stream.synchronize()
 
-    def train(self, X, T, steps: int, lr: float, batch: int, seed: int = 0, log_every: int = 0):
-        """Minibatch Adam on device-resident data; returns the loss history (sampled)."""
+    def train(self, X, T, steps: int, lr: float, batch: int, seed: int = 0, log_every: int = 0,
+              cosine: bool = True):
+        """Minibatch Adam on device-resident data (learning rate decayed by a half
+        cosine when `cosine`); returns the loss history (sampled)."""
         Xd, Td = _dev(X, 3, self.device), _dev(T, 2, self.device)
         n = Xd.shape[0]
         batch = min(batch, n, self.max_batch)
@@ -135,7 +138,8 @@ class Mlp:
                 idx = perm[k * batch:(k + 1) * batch]
                 xb = Xd.index_select(0, idx).contiguous()
                 tb = Td.index_select(0, idx).contiguous()
-                _check(lib().mlp_train_step(self.ctx, xb.data_ptr(), tb.data_ptr(), xb.shape[0], lr,
+                lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps)) if cosine else lr
+                _check(lib().mlp_train_step(self.ctx, xb.data_ptr(), tb.data_ptr(), xb.shape[0], lr_s,
                                             self.loss.data_ptr()), "mlp_train_step")
             if log_every and (s % log_every == 0 or s == steps - 1):
                 self.stream.synchronize()

@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 # relative rounding per population per step, so FP16 is held to the bulk
 # coexistence densities (column means) and to a loose per-node bound.
 TOL_F32_NODE = 1e-4
+TOL_F32A64_NODE = 1e-5   # FP32 storage, FP64 collision arithmetic
 TOL_F16_BULK = 2e-2
 TOL_F16_NODE = 0.35
 
@@ -30,7 +31,7 @@ def L():
     return lbm
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("scheme", [0, 1, 2])
 def test_deviation_storage_vs_oracle(L, prec, scheme):
     gp, op = pair(L, 96, 40, t=0.8, tau=1.0, scheme=scheme, sigma=0.1, precision=prec)
@@ -39,7 +40,7 @@ def test_deviation_storage_vs_oracle(L, prec, scheme):
     lat = L.Lattice(gp, rho0)
     lat.set_populations(f, 0)
     g0, _ = lat.get_populations()                 # the encoded start, decoded to FP64
-    assert np.max(np.abs(g0 - f)) < (1e-7 if prec == 1 else 1e-3)
+    assert np.max(np.abs(g0 - f)) < (1e-3 if prec == 2 else 1e-7)
     lat.step(1000)
     assert lat.status()[:2] == (L.LBM_OK, 1000)
     rho = lat.moments()[0]
@@ -51,6 +52,8 @@ def test_deviation_storage_vs_oracle(L, prec, scheme):
           f"bulk rho_l/rho_g error {bulk:.3e}")
     if prec == 1:
         assert node < TOL_F32_NODE
+    elif prec == 3:
+        assert node < TOL_F32A64_NODE
     else:
         assert bulk < TOL_F16_BULK and node < TOL_F16_NODE
     # mass bookkeeping is exact on the decoded fields
@@ -208,7 +211,7 @@ def test_full_size_droplet1024_sampled(L):
     lat.close()
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-5), (2, 3e-2)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-5), (2, 3e-2), (3, 1e-5)])
 def test_full_size_droplets4096_sampled(L, prec, tol):
     # 4096 x 4096, 64 droplets, C-S 0.7 Tc, tau 0.8, sigma 0.1 (the roofline workload)
     gp, op = pair(L, 4096, 4096, t=0.7, tau=0.8, scheme=2, sigma=0.1, precision=prec)
