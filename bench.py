@@ -112,6 +112,10 @@ def main():
                     help="comma-separated extra legs, or 'none'")
     ap.add_argument("--batch-steps", type=int, default=30000,
                     help="steps of the batched FP32-vs-FP64 coexistence comparison")
+    ap.add_argument("--tile", default=None, help="waves,rows,depth: fixed launch shape (no tuning)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a known-size kernel "
+                         "for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -122,9 +126,17 @@ def main():
 
     from paper_1204_4098_amd import lbm
 
+    if args.calibrate_copy:
+        a = torch.ones(args.calibrate_copy << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     nx, ny, rho0, kw, cfg = workload(args.workload, args.t_over_tc)
     res = time_lattice(lbm, torch, nx, ny, rho0, kw, args.precision, args.steps, args.warmup,
-                       args.graph_steps, not args.no_tune)
+                       args.graph_steps, not args.no_tune, tile)
     bpl = BYTES_PER_LUP[args.precision]
     achieved = bpl * nx * ny / (res["kernel_ms"] * 1e-3) / 1e9
     out = {
@@ -192,11 +204,13 @@ class Diverged(RuntimeError):
         self.step = step
 
 
-def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_steps, tune):
+def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_steps, tune, tile=None):
     """Warm up, then time `steps` steps between a device sync on both sides."""
     p = lbm.params(nx, ny, precision=precision, **kw)
     lat = lbm.Lattice(p, rho0, device="cuda:0")
-    if tune:
+    if tile:
+        lat.set_tile(*tile)
+    elif tune:
         lat.tune()
     tile = list(lat.get_tile())
     if graph_steps:
