@@ -84,26 +84,46 @@ __device__ constexpr int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ constexpr double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                                      1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
-// Pull the 9 populations of node (x, y) from the post-collision field.
+// Reciprocals: the hardware estimate refined by two Newton steps (FP64, about
+// 1 ulp), or the single-precision estimate (FP32 arithmetic paths, 1 ulp).
+// Arguments are positive normal numbers (or non-finite in a diverged state).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Column indices of one thread: its own column and the periodic neighbours.
+struct Cols {
+  unsigned x, xm, xp;
+};
+__device__ __forceinline__ Cols cols_of(int x, int nx) {
+  return Cols{(unsigned)x, (unsigned)(x == 0 ? nx - 1 : x - 1), (unsigned)(x == nx - 1 ? 0 : x + 1)};
+}
+
+// Pull the 9 populations of node (c.x, y) from the post-collision field.  Row
+// and plane offsets are uniform across the block (scalar registers); only the
+// 32-bit column index varies per lane.
 template <typename S>
-__device__ __forceinline__ void pull9(const typename Store<S>::E* __restrict__ src, const RunDev& d, int x, int y,
-                                      typename Store<S>::R (&f)[9]) {
-  const int xm = x == 0 ? d.nx - 1 : x - 1;
-  const int xp = x == d.nx - 1 ? 0 : x + 1;
+__device__ __forceinline__ void pull9(const typename Store<S>::E* __restrict__ src, const RunDev& d,
+                                      const Cols& c, int y, typename Store<S>::R (&f)[9]) {
   const int ym = y == 0 ? d.ny - 1 : y - 1;
   const int yp = y == d.ny - 1 ? 0 : y + 1;
   const int64_t P = d.plane;
-  const int64_t r0 = (int64_t)y * d.pitch, rm = (int64_t)ym * d.pitch, rp = (int64_t)yp * d.pitch;
   using T = Store<S>;
-  f[0] = T::ld(src + r0 + x);
-  f[1] = T::ld(src + P + r0 + xm);
-  f[2] = T::ld(src + 2 * P + rm + x);
-  f[3] = T::ld(src + 3 * P + r0 + xp);
-  f[4] = T::ld(src + 4 * P + rp + x);
-  f[5] = T::ld(src + 5 * P + rm + xm);
-  f[6] = T::ld(src + 6 * P + rm + xp);
-  f[7] = T::ld(src + 7 * P + rp + xp);
-  f[8] = T::ld(src + 8 * P + rp + xm);
+  const typename T::E* r0 = src + (int64_t)y * d.pitch;
+  const typename T::E* rm = src + (int64_t)ym * d.pitch;
+  const typename T::E* rp = src + (int64_t)yp * d.pitch;
+  f[0] = T::ld(r0 + c.x);
+  f[1] = T::ld(r0 + P + c.xm);
+  f[2] = T::ld(rm + 2 * P + c.x);
+  f[3] = T::ld(r0 + 3 * P + c.xp);
+  f[4] = T::ld(rp + 4 * P + c.x);
+  f[5] = T::ld(rm + 5 * P + c.xm);
+  f[6] = T::ld(rm + 6 * P + c.xp);
+  f[7] = T::ld(rp + 7 * P + c.xp);
+  f[8] = T::ld(rp + 8 * P + c.xm);
 }
 
 // Density deviation sum_a s_a in the arithmetic type (pairwise order).
@@ -117,9 +137,12 @@ __device__ __forceinline__ double psi2_of(double rho, const RunDev& d) {
   double p;
   if (d.eos == 0) {
     const double e = d.c1 * rho, m = 1.0 - e;
-    p = rho * d.RT * (1.0 + e * (1.0 + e * (1.0 - e))) / (m * m * m) - d.c2 * rho * rho;
+    p = rho * d.RT * (1.0 + e * (1.0 + e * (1.0 - e))) * rcp(m * m * m) - d.c2 * rho * rho;
   } else {
-    p = rho * d.RT / (1.0 - d.c1 * rho) - d.c2 * rho * rho / (1.0 + d.c1 * rho * (2.0 - d.c1 * rho));
+    const double b = d.c1 * rho;
+    // rho RT/(1 - b) - c2 rho^2/(1 + b(2 - b)) over one common reciprocal
+    const double q1 = 1.0 - b, q2 = 1.0 + b * (2.0 - b);
+    p = (rho * d.RT * q2 - d.c2 * rho * rho * q1) * rcp(q1 * q2);
   }
   return (p - rho * (1.0 / 3.0)) * d.two_over_G;
 }
@@ -150,7 +173,7 @@ __device__ __forceinline__ void force3x3(const double* rs, const double* rc, con
 template <typename R>
 __device__ __forceinline__ void collide(R (&s)[9], R drho, R rho, R jx, R jy, R Fx, R Fy,
                                         R inv_psi2, const RunDev& d) {
-  const R inv_rho = R(1) / rho;
+  const R inv_rho = rcp(rho);
   const R ux = jx * inv_rho, uy = jy * inv_rho;
   const R Fr_x = Fx * inv_rho, Fr_y = Fy * inv_rho;
   const R wx = ux + R(d.c_eq) * Fr_x, wy = uy + R(d.c_eq) * Fr_y;
@@ -199,6 +222,7 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
   const int tid = threadIdx.x;
   const bool act = tid < ncols;
   const int x = x0 + tid;
+  const Cols cx = cols_of(act ? x : x0, d.nx);
   const int xl = x0 == 0 ? d.nx - 1 : x0 - 1;
   const int xr = x0 + ncols >= d.nx ? 0 : x0 + ncols;
   const double rref = d.rho_ref;
@@ -210,7 +234,7 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
     int yy = y0 - 1 + k;
     yy = yy < 0 ? yy + d.ny : (yy >= d.ny ? yy - d.ny : yy);
     R f[9];
-    pull9<S>(src, d, (i & 1) ? xr : xl, yy, f);
+    pull9<S>(src, d, cols_of((i & 1) ? xr : xl, d.nx), yy, f);
     const double rho = rref + double(sum9(f));
     ((i & 1) ? haloR : haloL)[k] = sqrt(psi2_of(rho, d));
   }
@@ -220,9 +244,9 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
   double psi2c = 0.0;
   if (act) {
     R f[9];
-    pull9<S>(src, d, x, y0 == 0 ? d.ny - 1 : y0 - 1, f);
-    pull9<S>(src, d, x, y0, fc);
-    if (PF == 2) pull9<S>(src, d, x, y0 + 1 == d.ny ? 0 : y0 + 1, fn);
+    pull9<S>(src, d, cx, y0 == 0 ? d.ny - 1 : y0 - 1, f);
+    pull9<S>(src, d, cx, y0, fc);
+    if (PF == 2) pull9<S>(src, d, cx, y0 + 1 == d.ny ? 0 : y0 + 1, fn);
     ring[0][tid + 1] = sqrt(psi2_of(rref + double(sum9(f)), d));
     psi2c = psi2_of(rref + double(sum9(fc)), d);
     ring[1][tid + 1] = sqrt(psi2c);
@@ -243,9 +267,9 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
     double psi2n = 0.0;
     if (act) {
       if (PF == 2) {
-        if (j + 1 < nrows) pull9<S>(src, d, x, yn + 1 == d.ny ? 0 : yn + 1, fnn);
+        if (j + 1 < nrows) pull9<S>(src, d, cx, yn + 1 == d.ny ? 0 : yn + 1, fnn);
       } else {
-        pull9<S>(src, d, x, yn, fn);
+        pull9<S>(src, d, cx, yn, fn);
       }
       psi2n = psi2_of(rref + double(sum9(fn)), d);
       ring[sl][tid + 1] = sqrt(psi2n);
@@ -261,11 +285,11 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
       const R drho = sum9(fc);
       const double rho64 = rref + double(drho);
       bad |= !(psi2c > 0.0) || !(rho64 > 0.0);
-      const R ip2 = d.sig != 0.0 ? R(1.0 / psi2c) : R(0);
+      const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
       collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
-      const int64_t o = (int64_t)y * d.pitch + x;
+      typename T::E* row = dst + (int64_t)y * d.pitch;
 #pragma unroll
-      for (int a = 0; a < 9; ++a) T::st(dst + a * d.plane + o, fc[a]);
+      for (int a = 0; a < 9; ++a) T::st(row + a * d.plane + cx.x, fc[a]);
 #pragma unroll
       for (int a = 0; a < 9; ++a) fc[a] = fn[a];
       psi2c = psi2n;
@@ -364,7 +388,7 @@ __global__ void k_moments1(const typename Store<S>::E* __restrict__ src, RunDev 
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= d.nx) return;
   R f[9];
-  pull9<S>(src, d, x, y, f);
+  pull9<S>(src, d, cols_of(x, d.nx), y, f);
   const R drho = sum9(f);
   const double r = d.rho_ref + double(drho);
   const int64_t o = (int64_t)y * d.nx + x;
