@@ -151,7 +151,7 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes);
  * `rows` rows; rows = 0 selects the balanced schedule, in which a grid sized
  * to the GPU's resident capacity splits all strip rows evenly.  `depth` (1 or
  * 2) is how many rows of loads are in flight while a row is collided.
- * waves in {1, 2, 4}; rows in [0, 128].  lbm_tune times the candidates on the
+ * waves in {1, 2, 4, 8, 16}; rows in [0, 128].  lbm_tune times the candidates on the
  * current state without advancing it and keeps the fastest; the choice is
  * cached per (nx, ny, precision) for the life of the process.  Every tile
  * gives bitwise identical results. */
@@ -191,7 +191,7 @@ int lbm_batch_coexistence(lbm_batch* b, double* rho_l, double* rho_g, int32_t* s
 int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double* vy, double* p);
 int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f);
 /* Tiles of the batch work list (rows = 0: one item per strip of up to 128
- * rows), tuned over the whole batch like lbm_tune. */
+ * rows), tuned over the whole batch like lbm_tune; waves in {1, 2, 4, 8}. */
 int lbm_batch_tune(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth);
 int lbm_batch_set_tile(lbm_batch* b, int32_t waves, int32_t rows, int32_t depth);
 int lbm_batch_get_tile(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth);

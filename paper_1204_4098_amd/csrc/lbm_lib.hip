@@ -228,7 +228,11 @@ hipError_t launch_step_s(const Tile& t, const void* src, void* dst, const RunDev
     case 21: return launch_step_t<S, 2, 1>(src, dst, d, t.L, base, local, flag, st);
     case 22: return launch_step_t<S, 2, 2>(src, dst, d, t.L, base, local, flag, st);
     case 41: return launch_step_t<S, 4, 1>(src, dst, d, t.L, base, local, flag, st);
-    default: return launch_step_t<S, 4, 2>(src, dst, d, t.L, base, local, flag, st);
+    case 42: return launch_step_t<S, 4, 2>(src, dst, d, t.L, base, local, flag, st);
+    case 81: return launch_step_t<S, 8, 1>(src, dst, d, t.L, base, local, flag, st);
+    case 82: return launch_step_t<S, 8, 2>(src, dst, d, t.L, base, local, flag, st);
+    case 161: return launch_step_t<S, 16, 1>(src, dst, d, t.L, base, local, flag, st);
+    default: return launch_step_t<S, 16, 2>(src, dst, d, t.L, base, local, flag, st);
   }
 }
 
@@ -265,7 +269,9 @@ hipError_t launch_batch_s(const Tile& t, const void* src, void* dst, const RunDe
     case 21: return launch_batch_t<S, 2, 1>(src, dst, runs, items, nitems, base, local, flags, st);
     case 22: return launch_batch_t<S, 2, 2>(src, dst, runs, items, nitems, base, local, flags, st);
     case 41: return launch_batch_t<S, 4, 1>(src, dst, runs, items, nitems, base, local, flags, st);
-    default: return launch_batch_t<S, 4, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 42: return launch_batch_t<S, 4, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 81: return launch_batch_t<S, 8, 1>(src, dst, runs, items, nitems, base, local, flags, st);
+    default: return launch_batch_t<S, 8, 2>(src, dst, runs, items, nitems, base, local, flags, st);
   }
 }
 
@@ -374,8 +380,15 @@ size_t ctx_layout(const lbm_params& p, size_t* pop, size_t* aux, size_t* parts, 
 
 bool same_tile(const Tile& a, const Tile& b) { return a.nw == b.nw && a.L == b.L && a.pf == b.pf; }
 
-bool valid_tile(int nw, int L, int pf) {
-  return (nw == 1 || nw == 2 || nw == 4) && L >= 0 && L <= LMAX && (pf == 1 || pf == 2);
+// Strip widths of the single-lattice kernel (64 to 1024 columns) and of the
+// batched one (64 to 512 columns; batched lattices are at most a few hundred
+// columns wide).
+constexpr int kStepWaves[] = {1, 2, 4, 8, 16};
+constexpr int kBatchWaves[] = {1, 2, 4, 8};
+
+bool valid_tile(int nw, int L, int pf, int maxnw) {
+  return (nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16) && nw <= maxnw && L >= 0 &&
+         L <= LMAX && (pf == 1 || pf == 2);
 }
 
 void drop_graphs(lbm_ctx* c) {
@@ -674,7 +687,7 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
 }
 
 int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth) {
-  if (!c || !valid_tile(nw, L, depth)) return LBM_EINVAL;
+  if (!c || !valid_tile(nw, L, depth, 16)) return LBM_EINVAL;
   c->tile = Tile{nw, L, depth};
   return LBM_OK;
 }
@@ -694,7 +707,7 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out) {
   const int s = c->cur;
   const int64_t nodes = (int64_t)c->p.nx * c->p.ny;
   const int reps = nodes >= (1 << 22) ? 3 : 10;
-  for (int nw : {1, 2, 4}) {
+  for (int nw : kStepWaves) {
     if (nw > 1 && 64 * (nw / 2) >= c->p.nx) continue;
     for (int pf : {1, 2})
       for (int L : {0, 4, 8, 16, 32, 64, 128}) {
@@ -1009,7 +1022,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
 }
 
 int lbm_batch_set_tile(lbm_batch* b, int32_t nw, int32_t L, int32_t depth) {
-  if (!b || !valid_tile(nw, L, depth) || (L > 0 && L < 4)) return LBM_EINVAL;
+  if (!b || !valid_tile(nw, L, depth, 8) || (L > 0 && L < 4)) return LBM_EINVAL;
   batch_drop_graphs(b);
   return batch_items(b, Tile{nw, L, depth});
 }
@@ -1037,7 +1050,7 @@ int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth
   const int s = b->cur;
   int maxnx = 0;
   for (int r = 0; r < b->nruns; ++r) maxnx = std::max(maxnx, b->p[r].nx);
-  for (int nw : {1, 2, 4}) {
+  for (int nw : kBatchWaves) {
     if (nw > 1 && 64 * (nw / 2) >= maxnx) continue;
     for (int pf : {1, 2})
       for (int L : {0, 4, 8, 16, 32, 64}) {

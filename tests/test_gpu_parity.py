@@ -102,7 +102,7 @@ def test_tile_shapes_bitwise_identical(L):
     rho0 = slab_rho(200, 90, CS, 0.8, seed=3)
     outs = []
     for tile in [(1, 4, 1), (1, 16, 2), (2, 8, 1), (4, 128, 2), (4, 5, 2), (2, 33, 1), (1, 0, 2),
-                 (4, 0, 1), (2, 0, 2)]:
+                 (4, 0, 1), (2, 0, 2), (8, 0, 2), (16, 7, 1)]:
         lat = L.Lattice(gp, rho0)
         lat.set_tile(*tile)
         lat.step(37)
@@ -110,6 +110,25 @@ def test_tile_shapes_bitwise_identical(L):
         lat.close()
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+def test_wide_strips_bitwise_identical(L):
+    # 1100 columns: two 512-column strips plus a 76-column tail, or one
+    # 1024-column strip plus the tail; every strip width gives the same bits
+    gp, op = pair(L, 1100, 40, t=0.8, tau=0.9, scheme=2, sigma=0.1)
+    rho0 = slab_rho(1100, 40, CS, 0.8, seed=4)
+    outs = []
+    for tile in [(1, 8, 1), (8, 0, 2), (8, 16, 1), (16, 0, 2), (16, 5, 1), (4, 0, 2)]:
+        lat = L.Lattice(gp, rho0)
+        lat.set_tile(*tile)
+        lat.step(21)
+        outs.append(lat.get_populations()[0])
+        lat.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    f = olbm.init_equilibrium(rho0)
+    assert olbm.step(op, f, 21)[0] == 0
+    assert rel_err(outs[0], f) < TOL64
 
 
 def test_graph_replay_bitwise(L):

@@ -93,7 +93,7 @@ def _batch_runs(L, prec=0):
     return gps, ops, rhos
 
 
-@pytest.mark.parametrize("tile", [(1, 16, 2), (2, 0, 1), (4, 8, 2)])
+@pytest.mark.parametrize("tile", [(1, 16, 2), (2, 0, 1), (4, 8, 2), (8, 0, 2)])
 def test_batch_equals_single_runs_bitwise(L, tile):
     gps, _, rhos = _batch_runs(L)
     b = L.Batch(gps, rhos)
