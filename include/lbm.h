@@ -66,7 +66,18 @@ enum {
 };
 
 enum { LBM_EOS_CS = 0, LBM_EOS_PR = 1 };
-enum { LBM_SCHEME_SHANCHEN = 0, LBM_SCHEME_EDM = 1, LBM_SCHEME_IMPROVED = 2 };
+/* Forcing schemes.  SHANCHEN: velocity shift, Eqs. (9)-(10).  EDM: exact
+ * difference method, Eq. (11).  IMPROVED: Eq. (31) (sigma = 0 is Guo et al.'s
+ * scheme, Eq. (13)).  EDM_MODIFIED: EDM with C_e = 1/tau in the general form of
+ * Eq. (12) (Sec. III.C).  LADD: Table I, equilibrium and forcing velocity u,
+ * B_e = C_e = 1. */
+enum {
+  LBM_SCHEME_SHANCHEN = 0,
+  LBM_SCHEME_EDM = 1,
+  LBM_SCHEME_IMPROVED = 2,
+  LBM_SCHEME_EDM_MODIFIED = 3,
+  LBM_SCHEME_LADD = 4
+};
 /* Storage of populations: FP64, or deviations d_a = f_a - w_a rho_ref stored
  * in FP32 / FP16 with FP32 collision arithmetic (the EOS, psi and force stay
  * FP64), or FP32 deviations with FP64 collision arithmetic.  rho_ref = 0 stores

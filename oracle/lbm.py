@@ -15,7 +15,7 @@ import numpy as np
 from . import build as _build
 
 EOS_CS, EOS_PR = 0, 1
-SCHEME_SC, SCHEME_EDM, SCHEME_IMPROVED = 0, 1, 2
+SCHEME_SC, SCHEME_EDM, SCHEME_IMPROVED, SCHEME_EDM_MODIFIED, SCHEME_LADD = 0, 1, 2, 3, 4
 OK, EINVAL, EPSI, EDIVERGED = 0, -1, -2, -3
 
 EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])

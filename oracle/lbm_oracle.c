@@ -20,6 +20,10 @@
  *   Sec. III.A, Eq. (11)       exact-difference method (EDM)
  *   Sec. III.C, Eq. (23)       Carnahan-Starling equation of state
  *   Sec. IV.B, Eq. (31)        improved forcing scheme (sigma = 0: Guo et al.)
+ *   Sec. III.B, Eq. (12)       general form of a forcing term, used literally for
+ *                              Ladd's scheme (Table I: equilibrium and forcing
+ *                              velocity u, B_e = C_e = 1) and the modified EDM
+ *                              (Sec. III.C: EDM with C_e = 1/tau)
  * Peng-Robinson is not written in the paper; its standard form is used
  * (alpha(T) = [1 + kappa (1 - sqrt(T/Tc))]^2,
  *  kappa = 0.37464 + 1.54226 w - 0.26992 w^2).
@@ -31,6 +35,8 @@
  *   - In Eq. (31), upsilon = tau - 1/2 exactly.
  *   - The velocity in the equilibrium of the improved scheme is the actual
  *     fluid velocity v = u + F/(2 rho), as in Guo et al.'s scheme.
+ *   - Modified EDM: only C_e changes; B_e = 1, the forcing velocity is EDM's
+ *     v = u + F/(2 rho) and the equilibrium is taken at u, as in EDM.
  *   - Periodic boundaries in x and y.
  *   - Divergence: a non-finite or non-positive density, or a non-positive
  *     (or non-finite) argument of the square root in Eq. (8).
@@ -43,7 +49,8 @@
 #include <string.h>
 
 enum { OR_EOS_CS = 0, OR_EOS_PR = 1 };
-enum { OR_SCHEME_SC = 0, OR_SCHEME_EDM = 1, OR_SCHEME_IMPROVED = 2 };
+enum { OR_SCHEME_SC = 0, OR_SCHEME_EDM = 1, OR_SCHEME_IMPROVED = 2, OR_SCHEME_EDM_MODIFIED = 3,
+       OR_SCHEME_LADD = 4 };
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EPSI = -2, OR_EDIVERGED = -3, OR_ENOMEM = -5 };
 
 typedef struct {
@@ -145,9 +152,36 @@ void or_interaction_force(const or_params* p, const double* psi, double* Fx, dou
  *   improved (Eq. 31): u_eq = v = u + F/(2 rho), v' = v + sigma F / ((tau - 1/2) psi^2),
  *                     F_a = w (1 - 1/(2 tau)) [(e - v')/c_s^2 + (e.v') e / c_s^4] . F
  * psi2 is psi^2 (used by the improved scheme only). */
+/* Eq. (12): F_a = w_a [B.e_a / c_s^2 + C:(e_a e_a - c_s^2 I) / (2 c_s^4)], with
+ * the vector B and the symmetric 2x2 tensor C (row-major Cxx, Cxy, Cyx, Cyy). */
+void or_general_form(const double B[2], const double C[4], double* Fa) {
+  for (int a = 0; a < 9; ++a) {
+    double e[2] = {EX[a], EY[a]};
+    double first = (B[0] * e[0] + B[1] * e[1]) / CS2;
+    double second = 0.0;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) second += C[2 * i + j] * (e[i] * e[j] - (i == j ? CS2 : 0.0));
+    Fa[a] = WEQ[a] * (first + second / (2.0 * CS2 * CS2));
+  }
+}
+
 void or_forcing(const or_params* p, double rho, double ux, double uy, double Fx, double Fy,
                 double psi2, double* ueqx, double* ueqy, double* Fa) {
-  if (p->scheme == OR_SCHEME_SC) {
+  if (p->scheme == OR_SCHEME_EDM_MODIFIED || p->scheme == OR_SCHEME_LADD) {
+    /* forcing velocity: EDM's v = u + F/(2 rho) (modified EDM) or u (Ladd) */
+    double vx = ux, vy = uy, Ce = 1.0;
+    if (p->scheme == OR_SCHEME_EDM_MODIFIED) {
+      vx = ux + Fx / (2.0 * rho);
+      vy = uy + Fy / (2.0 * rho);
+      Ce = 1.0 / p->tau;
+    }
+    double B[2] = {Fx, Fy};  /* B_e = 1 */
+    double C[4] = {Ce * (vx * Fx + Fx * vx), Ce * (vx * Fy + Fx * vy),
+                   Ce * (vy * Fx + Fy * vx), Ce * (vy * Fy + Fy * vy)};
+    *ueqx = ux;
+    *ueqy = uy;
+    or_general_form(B, C, Fa);
+  } else if (p->scheme == OR_SCHEME_SC) {
     *ueqx = ux + p->tau * Fx / rho;
     *ueqy = uy + p->tau * Fy / rho;
     for (int a = 0; a < 9; ++a) Fa[a] = 0.0;
@@ -178,7 +212,7 @@ static int valid_params(const or_params* p) {
   if (p->nx < 3 || p->ny < 3) return 0;
   if (!(p->tau > 0.5)) return 0;
   if (p->eos != OR_EOS_CS && p->eos != OR_EOS_PR) return 0;
-  if (p->scheme < OR_SCHEME_SC || p->scheme > OR_SCHEME_IMPROVED) return 0;
+  if (p->scheme < OR_SCHEME_SC || p->scheme > OR_SCHEME_LADD) return 0;
   if (p->eos == OR_EOS_PR && !(p->Tc > 0.0)) return 0;
   if (!(p->G != 0.0)) return 0;
   return 1;

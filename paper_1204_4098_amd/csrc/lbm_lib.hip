@@ -59,7 +59,7 @@ int validate(const lbm_params& p) {
   if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return LBM_EINVAL;
   if (!(p.G != 0.0) || !std::isfinite(p.G)) return LBM_EINVAL;
   if (p.eos != LBM_EOS_CS && p.eos != LBM_EOS_PR) return LBM_EINVAL;
-  if (p.scheme < LBM_SCHEME_SHANCHEN || p.scheme > LBM_SCHEME_IMPROVED) return LBM_EINVAL;
+  if (p.scheme < LBM_SCHEME_SHANCHEN || p.scheme > LBM_SCHEME_LADD) return LBM_EINVAL;
   if (p.precision < LBM_PREC_F64 || p.precision > LBM_PREC_F32DEV_F64) return LBM_EINVAL;
   if (!(p.a > 0) || !(p.b > 0) || !(p.R > 0) || !(p.T > 0)) return LBM_EINVAL;
   if (!std::isfinite(p.sigma)) return LBM_EINVAL;
@@ -102,6 +102,19 @@ RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64
     case LBM_SCHEME_EDM:  // Eq. (11) = Eq. (16): B_e = C_e = 1, velocity u + F/(2 rho)
       d.c_eq = 0.0;
       d.c_f = 0.5;
+      d.sig = 0.0;
+      d.Be = d.Ce = 1.0;
+      break;
+    case LBM_SCHEME_EDM_MODIFIED:  // Sec. III.C: EDM with C_e = 1/tau
+      d.c_eq = 0.0;
+      d.c_f = 0.5;
+      d.sig = 0.0;
+      d.Be = 1.0;
+      d.Ce = 1.0 / p.tau;
+      break;
+    case LBM_SCHEME_LADD:  // Table I: u in the equilibrium and in F_a, B_e = C_e = 1
+      d.c_eq = 0.0;
+      d.c_f = 0.0;
       d.sig = 0.0;
       d.Be = d.Ce = 1.0;
       break;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
 
 LBM_OK, LBM_EINVAL, LBM_EPSI, LBM_EDIVERGED, LBM_EHIP, LBM_ENOSPACE, LBM_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 LBM_EOS_CS, LBM_EOS_PR = 0, 1
-LBM_SCHEME_SHANCHEN, LBM_SCHEME_EDM, LBM_SCHEME_IMPROVED = 0, 1, 2
+LBM_SCHEME_SHANCHEN, LBM_SCHEME_EDM, LBM_SCHEME_IMPROVED, LBM_SCHEME_EDM_MODIFIED, LBM_SCHEME_LADD = 0, 1, 2, 3, 4
 LBM_PREC_F64, LBM_PREC_F32DEV, LBM_PREC_F16DEV, LBM_PREC_F32DEV_F64 = 0, 1, 2, 3
 
 

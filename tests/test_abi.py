@@ -52,6 +52,11 @@ def test_strerror_and_invalid_params(L):
     p = L.params(2, 32, T=0.08)
     with pytest.raises(L.LbmError):
         L.lbm_workspace_bytes(p)
+    for scheme in (-1, 5):
+        with pytest.raises(L.LbmError):
+            L.lbm_workspace_bytes(L.params(64, 32, T=0.08, scheme=scheme))
+    for scheme in range(5):
+        assert L.lbm_workspace_bytes(L.params(64, 32, T=0.08, scheme=scheme)) > 0
     assert L.lbm_workspace_bytes(L.params(64, 32, T=0.08)) >= 2 * 9 * 64 * 32 * 8
 
 

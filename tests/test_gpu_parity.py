@@ -52,12 +52,14 @@ def test_config0_slab_10000_steps(L, sigma):
     assert np.max(np.abs(g - f)) < 1e-10 * np.max(np.abs(f))
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("tau", [0.6, 1.0, 1.5])
 def test_schemes_ragged_tiles(L, scheme, tau):
-    # ragged 67 x 29 lattice cut into 1-wave strips of 8 rows: several tiles, ragged tails
-    gp, op = pair(L, 67, 29, t=0.85, tau=tau, scheme=scheme, sigma=0.105)
-    rho0 = slab_rho(67, 29, CS, 0.85, noise=0.01, seed=7)
+    # ragged 67 x 29 lattice cut into 1-wave strips of 8 rows: several tiles, ragged tails;
+    # Ladd's scheme (4) is stable on this interface only closer to Tc
+    t = 0.95 if scheme == 4 else 0.85
+    gp, op = pair(L, 67, 29, t=t, tau=tau, scheme=scheme, sigma=0.105)
+    rho0 = slab_rho(67, 29, CS, t, noise=0.01, seed=7)
     errs, _, _ = _run_both(L, gp, op, rho0, [1, 50, 300], tile=(1, 8))
     assert max(errs) < TOL64, errs
 

@@ -82,7 +82,9 @@ def _batch_runs(L, prec=0):
              dict(nx=160, ny=48, t=0.9, tau=1.3, scheme=0, sigma=0.0, eos=CS),
              dict(nx=64, ny=64, t=0.85, tau=0.9, scheme=1, sigma=0.0, eos=CS),
              dict(nx=130, ny=20, t=0.8, tau=1.0, scheme=2, sigma=0.105, eos=PR),
-             dict(nx=512, ny=16, t=0.75, tau=0.6, scheme=2, sigma=0.2, eos=CS)]
+             dict(nx=512, ny=16, t=0.75, tau=0.6, scheme=2, sigma=0.2, eos=CS),
+             dict(nx=96, ny=16, t=0.7, tau=0.7, scheme=3, sigma=0.0, eos=CS),
+             dict(nx=64, ny=32, t=0.95, tau=1.2, scheme=4, sigma=0.0, eos=CS)]
     gps, ops, rhos = [], [], []
     for i, s in enumerate(specs):
         gp, op = pair(L, s["nx"], s["ny"], t=s["t"], tau=s["tau"], scheme=s["scheme"],
