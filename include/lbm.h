@@ -139,6 +139,19 @@ int lbm_moments(lbm_ctx* c, double* rho, double* vx, double* vy, double* p);
 /* Same, into device arrays (ny*nx each, FP64, non-null), asynchronous. */
 int lbm_moments_device(lbm_ctx* c, double* rho, double* vx, double* vy, double* p);
 
+/* Flat-interface diagnostic for an interface whose normal is x (the slab
+ * initial condition).  rho_bar (nx host doubles, non-null) = mean of rho over
+ * y for each column.  p_n (nx host doubles, nullable) = normal pressure of
+ * Eq. (25) with alpha = 0, beta = 3 (nearest-neighbour stencil, Sec. IV.A)
+ * plus the improved scheme's 2 G^2 sigma psi'^2 (Eq. 35), from psi(rho_bar)
+ * of Eq. (8) with central differences psi' = (psi[x+1] - psi[x-1])/2 and
+ * psi'' = psi[x+1] - 2 psi[x] + psi[x-1], periodic.  At equilibrium p_n is
+ * constant across the interface.  The paper fixes the scheme's contribution
+ * to p_n only for the improved scheme (sigma = 0: Guo et al.), so p_n for
+ * any other scheme returns LBM_ENOTSUP.  Uses the context's device scratch;
+ * synchronous.  A column mean outside the range of Eq. (8) gives NaN there. */
+int lbm_flat_profile(lbm_ctx* c, double* rho_bar, double* p_n);
+
 /* Total mass: fixed[0..1] = the 128-bit integer sum over nodes of
  * round-to-nearest-even(rho * 2^40) as (low, high) 64-bit words, with
  * rho = sum_a f_a summed in direction order 0..8 in FP64 (populations decoded

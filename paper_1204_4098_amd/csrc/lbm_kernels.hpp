@@ -419,6 +419,31 @@ __global__ void k_moments2(RunDev d, const double* __restrict__ psi, const doubl
   p[o] = pressure_of(r, d);
 }
 
+// Flat interface with normal x: mean density of each column (fixed order in y).
+__global__ void k_colmean(const double* __restrict__ rho, int nx, int ny, double* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  double s = 0.0;
+  for (int y = 0; y < ny; ++y) s += rho[(int64_t)y * nx + x];
+  out[x] = s / ny;
+}
+
+// Normal pressure across the profile (Eq. 25 with alpha = 0, beta = 3, plus the
+// improved scheme's 2 G^2 sigma psi'^2 of Eq. 35); psi' and psi'' are central
+// differences, periodic in x.
+__global__ void k_normal_pressure(const double* __restrict__ rbar, RunDev d, double sigma,
+                                  double* __restrict__ pn) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= d.nx) return;
+  const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+  const double pm = sqrt(psi2_of(rbar[xm], d)), pc = sqrt(psi2_of(rbar[x], d)),
+               pp = sqrt(psi2_of(rbar[xp], d));
+  const double d1 = 0.5 * (pp - pm), d2 = (pp - 2.0 * pc) + pm;
+  const double G = -d.mG;
+  pn[x] = rbar[x] * (1.0 / 3.0) + 0.5 * G * pc * pc + (G / 12.0) * (3.0 * pc * d2) +
+          2.0 * G * G * sigma * d1 * d1;
+}
+
 // Decode one stored population to FP64 exactly as the host decoder does:
 // f = s + (w * rho_ref), two separately rounded operations.
 __device__ __forceinline__ double decode(double v, int, double) { return v; }

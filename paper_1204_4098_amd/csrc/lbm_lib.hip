@@ -619,6 +619,27 @@ int lbm_moments(lbm_ctx* c, double* rho, double* vx, double* vy, double* p) {
   return lbm_status(c, nullptr, nullptr);
 }
 
+int lbm_flat_profile(lbm_ctx* c, double* rho_bar, double* p_n) {
+  if (!c || !rho_bar) return LBM_EINVAL;
+  if (p_n && c->p.scheme != LBM_SCHEME_IMPROVED) return LBM_ENOTSUP;
+  const size_t n = (size_t)c->p.nx * c->p.ny;
+  double* a = c->aux;
+  // rho plane at a; the column means and the pressure reuse the velocity plane
+  double* rb = a + n;
+  double* pn = rb + c->p.nx;
+  HIPCHK(launch_moments(c->p.precision, c->buf[c->cur], c->d, a, a + n, a + 2 * n, a + 3 * n,
+                        a + 4 * n, c->st));
+  const dim3 blk(256), grd((c->p.nx + 255) / 256);
+  hipLaunchKernelGGL(k_colmean, grd, blk, 0, c->st, (const double*)a, c->p.nx, c->p.ny, rb);
+  if (p_n)
+    hipLaunchKernelGGL(k_normal_pressure, grd, blk, 0, c->st, (const double*)rb, c->d, c->p.sigma, pn);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(rho_bar, rb, c->p.nx * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  if (p_n) HIPCHK(hipMemcpyAsync(p_n, pn, c->p.nx * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return lbm_status(c, nullptr, nullptr);
+}
+
 int lbm_mass(lbm_ctx* c, int64_t* fixed, double* mass) {
   if (!c) return LBM_EINVAL;
   HIPCHK(launch_mass(c->p.precision, c->buf[c->cur], c->d, c->part_i, c->part_d, c->st));

@@ -56,6 +56,7 @@ _SIGS = {
     "lbm_moments": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_moments_device": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_mass": (C.c_int, [_vp, _lp, _dp]),
+    "lbm_flat_profile": (C.c_int, [_vp, _vp, _vp]),
     "lbm_get_populations": (C.c_int, [_vp, _vp, _lp]),
     "lbm_set_populations": (C.c_int, [_vp, _vp, C.c_int64]),
     "lbm_state_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
@@ -199,6 +200,15 @@ class Lattice:
         if check or st not in (LBM_OK, LBM_EDIVERGED):
             _check(st, "lbm_moments")
         return tuple(out)
+
+    def flat_profile(self, pressure: bool = True):
+        """(rho_bar, p_n): y-mean density per column and the normal pressure of
+        Eqs. (25)/(35) across an interface with normal x (p_n: improved scheme)."""
+        rb = np.empty(self.p.nx)
+        pn = np.empty(self.p.nx) if pressure else None
+        _check(lib().lbm_flat_profile(self.ctx, rb.ctypes.data, None if pn is None else pn.ctypes.data),
+               "lbm_flat_profile")
+        return rb, pn
 
     def moments_device(self):
         out = [torch.empty((self.p.ny, self.p.nx), dtype=torch.float64, device=self.device) for _ in range(4)]
