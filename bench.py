@@ -112,7 +112,9 @@ def main():
                     help="comma-separated extra legs, or 'none'")
     ap.add_argument("--batch-steps", type=int, default=30000,
                     help="steps of the batched FP32-vs-FP64 coexistence comparison")
-    ap.add_argument("--tile", default=None, help="waves,rows,depth: fixed launch shape (no tuning)")
+    ap.add_argument("--tile", default=None,
+                    help="waves,rows,depth[,steps]: fixed launch shape (no tuning); steps = time "
+                         "steps per launch (1, or 2 for the two-step kernel)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a known-size kernel "
                          "for scaling memory counters)")
@@ -138,7 +140,10 @@ def main():
     res = time_lattice(lbm, torch, nx, ny, rho0, kw, args.precision, args.steps, args.warmup,
                        args.graph_steps, not args.no_tune, tile)
     bpl = BYTES_PER_LUP[args.precision]
-    achieved = bpl * nx * ny / (res["kernel_ms"] * 1e-3) / 1e9
+    ts = res["tile"][3]                      # time steps per launch of the step kernel
+    launch_ms = res["kernel_ms"] * ts        # average duration of one launch
+    # algorithmic bytes of one launch: every population read once and written once
+    achieved = bpl * nx * ny / (launch_ms * 1e-3) / 1e9
     out = {
         "metric": "D2Q9 MLUPS & %HBM roofline; batched FP32 vs plain FP64 at <=1e-4 density err",
         "value": round(res["mlups"], 1),
@@ -157,8 +162,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_for(args.workload, args.precision, res["tile"]),
-                     "kernel": "k_step", "bytes_per_lup": bpl,
-                     "kernel_avg_us": round(res["kernel_ms"] * 1e3, 2)},
+                     "kernel": "k_step2" if ts == 2 else "k_step", "steps_per_launch": ts,
+                     "bytes_per_lup": bpl / ts, "kernel_avg_us": round(launch_ms * 1e3, 2),
+                     # MLUPS x the single-step 144 B/LUP over the peak (exceeds 1 only
+                     # when steps are fused; not a bandwidth)
+                     "single_step_equivalent_frac": round(
+                         bpl * nx * ny / (res["kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
     }
     log(f"main leg done: {out['value']} MLUPS, {out['roofline']['frac']:.3f} of HBM peak")
     legs = [] if args.legs == "none" else args.legs.split(",")
@@ -167,11 +176,11 @@ def main():
         for prec in (1, 2, 3):
             r = time_lattice(lbm, torch, nx, ny, rho0, kw, prec, args.steps, args.warmup,
                              args.graph_steps, not args.no_tune)
-            gbs = BYTES_PER_LUP[prec] * nx * ny / (r["kernel_ms"] * 1e-3) / 1e9
+            gbs = BYTES_PER_LUP[prec] * nx * ny / (r["kernel_ms"] * r["tile"][3] * 1e-3) / 1e9
             out["precision"][PREC_NAME[prec]] = {"mlups": round(r["mlups"], 1), "tile": r["tile"],
                                                  "achieved_gbs": round(gbs, 1),
                                                  "frac": round(gbs / PEAK_HBM_GBS, 4),
-                                                 "bytes_per_lup": BYTES_PER_LUP[prec]}
+                                                 "bytes_per_lup": BYTES_PER_LUP[prec] / r["tile"][3]}
             log(f"precision {PREC_NAME[prec]}: {r['mlups']:.0f} MLUPS")
     if "droplet1024" in legs and args.workload != "droplet1024":
         d = {}
@@ -247,6 +256,8 @@ def traffic_for(workload, precision, tile):
     except (OSError, ValueError):
         return None
     key = f"{workload}/{PREC_NAME[precision]}/{tile[0]}x{tile[1]}x{tile[2]}"
+    if len(tile) > 3 and tile[3] != 1:
+        key += f"x{tile[3]}steps"
     e = table.get("entries", {}).get(key)
     return None if e is None else e.get("bytes_per_launch")
 

@@ -175,13 +175,18 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes);
  * `rows` rows; rows = 0 selects the balanced schedule, in which a grid sized
  * to the GPU's resident capacity splits all strip rows evenly.  `depth` (1 or
  * 2) is how many rows of loads are in flight while a row is collided.
- * waves in {1, 2, 4, 8, 16}; rows in [0, 128].  lbm_tune times the candidates on the
- * current state without advancing it and keeps the fastest; the choice is
- * cached per (nx, ny, precision) for the life of the process.  Every tile
- * gives bitwise identical results. */
-int lbm_tune(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth);
-int lbm_set_tile(lbm_ctx* c, int32_t waves, int32_t rows, int32_t depth);
-int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth);
+ * `steps` (1 or 2) is the number of time steps one launch advances: with 2,
+ * the populations of the intermediate step stay on chip (registers and LDS),
+ * so they cross HBM once per two steps; its strips are 64*waves - 4 columns
+ * wide (the four extra columns are recomputed), waves in {4, 8}, and an odd
+ * remainder of lbm_step(n) runs one single step.
+ * waves in {1, 2, 4, 8, 16}; rows in [0, 128].  lbm_tune times the candidates
+ * on the current state without advancing it and keeps the fastest per lattice
+ * step; the choice is cached per (nx, ny, precision) for the life of the
+ * process.  Every tile gives bitwise identical results. */
+int lbm_tune(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
+int lbm_set_tile(lbm_ctx* c, int32_t waves, int32_t rows, int32_t depth, int32_t steps);
+int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
 
 /* Replay n steps through captured HIP graphs of k steps each (k even, >= 2;
  * 0 disables).  Needs a non-null stream.  Results are bitwise identical to

@@ -51,7 +51,8 @@ struct Item {
   int32_t run, x0, y0, ncols, nrows, pad;
 };
 
-// Storage traits: E = element type in memory, R = collision arithmetic type.
+// Storage traits: E = element type in memory, R = collision arithmetic type;
+// round(v) = the value a store followed by a load would give.
 struct f32s_f64a {};  // FP32 deviation storage with FP64 collision arithmetic
 template <typename S> struct Store;
 template <> struct Store<double> {
@@ -59,24 +60,28 @@ template <> struct Store<double> {
   using R = double;
   static __device__ __forceinline__ R ld(const E* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ R round(R v) { return v; }
 };
 template <> struct Store<float> {
   using E = float;
   using R = float;
   static __device__ __forceinline__ R ld(const E* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ R round(R v) { return v; }
 };
 template <> struct Store<f32s_f64a> {
   using E = float;
   using R = double;
   static __device__ __forceinline__ R ld(const E* p) { return double(__builtin_nontemporal_load(p)); }
   static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(float(v), p); }
+  static __device__ __forceinline__ R round(R v) { return double(float(v)); }
 };
 template <> struct Store<__half> {
   using E = __half;
   using R = float;
   static __device__ __forceinline__ R ld(const E* p) { return __half2float(*p); }
   static __device__ __forceinline__ void st(E* p, R v) { *p = __float2half_rn(v); }
+  static __device__ __forceinline__ R round(R v) { return __half2float(__float2half_rn(v)); }
 };
 
 __device__ constexpr int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -126,25 +131,34 @@ __device__ __forceinline__ void pull9(const typename Store<S>::E* __restrict__ s
   f[8] = T::ld(rp + 8 * P + c.xm);
 }
 
+// The arithmetic of one node update below is written with explicit fma()
+// where a fused multiply-add is wanted and compiled with contraction off, so
+// every kernel that inlines it performs the same operations and rounds the
+// same way (the single-step, two-step and batched kernels give identical bits).
+
 // Density deviation sum_a s_a in the arithmetic type (pairwise order).
 template <typename R>
 __device__ __forceinline__ R sum9(const R (&s)[9]) {
+#pragma clang fp contract(off)
   return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
 }
 
 // psi^2 = 2 (p_EOS(rho) - rho/3) / G in FP64 (Eq. 8 with Eq. 23 or Peng-Robinson).
 __device__ __forceinline__ double psi2_of(double rho, const RunDev& d) {
+#pragma clang fp contract(off)
   double p;
   if (d.eos == 0) {
+    // rho RT (1 + e + e^2 - e^3)/(1 - e)^3 - c2 rho^2, e = b rho / 4
     const double e = d.c1 * rho, m = 1.0 - e;
-    p = rho * d.RT * (1.0 + e * (1.0 + e * (1.0 - e))) * rcp(m * m * m) - d.c2 * rho * rho;
+    const double poly = fma(e, fma(e, 1.0 - e, 1.0), 1.0);
+    p = fma((rho * d.RT) * poly, rcp((m * m) * m), -((d.c2 * rho) * rho));
   } else {
-    const double b = d.c1 * rho;
     // rho RT/(1 - b) - c2 rho^2/(1 + b(2 - b)) over one common reciprocal
-    const double q1 = 1.0 - b, q2 = 1.0 + b * (2.0 - b);
-    p = (rho * d.RT * q2 - d.c2 * rho * rho * q1) * rcp(q1 * q2);
+    const double b = d.c1 * rho;
+    const double q1 = 1.0 - b, q2 = fma(b, 2.0 - b, 1.0);
+    p = fma(rho * d.RT, q2, -(((d.c2 * rho) * rho) * q1)) * rcp(q1 * q2);
   }
-  return (p - rho * (1.0 / 3.0)) * d.two_over_G;
+  return fma(rho, -1.0 / 3.0, p) * d.two_over_G;
 }
 
 __device__ __forceinline__ double pressure_of(double rho, const RunDev& d) {
@@ -159,38 +173,57 @@ __device__ __forceinline__ double pressure_of(double rho, const RunDev& d) {
 // s = y-1, c = y, n = y+1; index 0 = x-1, 1 = x, 2 = x+1), w(1)=1/3, w(2)=1/12.
 __device__ __forceinline__ void force3x3(const double* rs, const double* rc, const double* rn, int i,
                                          double mG, double& Fx, double& Fy) {
+#pragma clang fp contract(off)
   constexpr double w1 = 1.0 / 3.0, w2 = 1.0 / 12.0;
   const double dNE = rn[i + 1] - rs[i - 1];   // psi(x+e5) - psi(x-e5)
   const double dNW = rn[i - 1] - rs[i + 1];   // psi(x+e6) - psi(x-e6)
-  const double Sx = w1 * (rc[i + 1] - rc[i - 1]) + w2 * (dNE - dNW);
-  const double Sy = w1 * (rn[i] - rs[i]) + w2 * (dNE + dNW);
+  const double Sx = fma(w1, rc[i + 1] - rc[i - 1], w2 * (dNE - dNW));
+  const double Sy = fma(w1, rn[i] - rs[i], w2 * (dNE + dNW));
   const double c = mG * rc[i];
   Fx = c * Sx;
   Fy = c * Sy;
+}
+
+// e_a . (x, y) for the D2Q9 directions (components 0 or +-1: adds only).
+template <typename R>
+__device__ __forceinline__ R edot(int a, R x, R y) {
+#pragma clang fp contract(off)
+  switch (a) {
+    case 1: return x;
+    case 2: return y;
+    case 3: return -x;
+    case 4: return -y;
+    case 5: return x + y;
+    case 6: return y - x;
+    case 7: return -(x + y);
+    case 8: return x - y;
+    default: return R(0);
+  }
 }
 
 // BGK collision with the forcing scheme in general form (see RunDev).
 template <typename R>
 __device__ __forceinline__ void collide(R (&s)[9], R drho, R rho, R jx, R jy, R Fx, R Fy,
                                         R inv_psi2, const RunDev& d) {
+#pragma clang fp contract(off)
   const R inv_rho = rcp(rho);
   const R ux = jx * inv_rho, uy = jy * inv_rho;
   const R Fr_x = Fx * inv_rho, Fr_y = Fy * inv_rho;
-  const R wx = ux + R(d.c_eq) * Fr_x, wy = uy + R(d.c_eq) * Fr_y;
+  const R wx = fma(R(d.c_eq), Fr_x, ux), wy = fma(R(d.c_eq), Fr_y, uy);
   const R sg = R(d.sig) * inv_psi2;
-  const R vx = ux + R(d.c_f) * Fr_x + sg * Fx, vy = uy + R(d.c_f) * Fr_y + sg * Fy;
+  const R vx = fma(sg, Fx, fma(R(d.c_f), Fr_x, ux)), vy = fma(sg, Fy, fma(R(d.c_f), Fr_y, uy));
   const R om = R(d.inv_tau), Be3 = R(3.0 * d.Be), Ce = R(d.Ce);
-  const R usq = R(1.5) * (wx * wx + wy * wy);
-  const R vF3 = R(3) * (vx * Fx + vy * Fy);
+  const R usq = R(1.5) * fma(wx, wx, wy * wy);
+  const R vF3 = R(3) * fma(vx, Fx, vy * Fy);
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const R w = R(kW[a]);
-    const R eu = R(kEX[a]) * wx + R(kEY[a]) * wy;
-    const R seq = w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
-    const R eF = R(kEX[a]) * Fx + R(kEY[a]) * Fy;
-    const R ev = R(kEX[a]) * vx + R(kEY[a]) * vy;
-    const R Fa = w * (Be3 * eF + Ce * (R(9) * ev * eF - vF3));
-    s[a] = s[a] + om * (seq - s[a]) + Fa;
+    const R eu = edot(a, wx, wy), eF = edot(a, Fx, Fy), ev = edot(a, vx, vy);
+    // f_eq deviation w (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)), Eq. (2)
+    const R seq = w * fma(rho, fma(R(4.5) * eu, eu, fma(R(3), eu, -usq)), drho);
+    // forcing term w [3 B_e e.F + C_e (9 (e.v)(e.F) - 3 v.F)], Eq. (12)
+    const R Fa = w * fma(Be3, eF, Ce * fma(R(9) * ev, eF, -vF3));
+    s[a] = fma(om, seq - s[a], s[a]) + Fa;
   }
 }
 
@@ -344,6 +377,221 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
     n = min(n, LMAX);
     const int x0 = s * SW;
     tile_step<S, NW, PF>(src, dst, d, x0, y, min(SW, d.nx - x0), n, step, flag, ring, haloL, haloR);
+    r += n;
+    __syncthreads();  // LDS is reused by the next piece
+  }
+}
+
+// ---- two time steps per launch ------------------------------------------------
+//
+// The populations cross HBM once per two steps.  Lane i of a block owns
+// column c = x0 - 2 + i for both steps.  Step one (t -> t+1) runs on every
+// lane exactly as tile_step does and leaves f*(t+1) in registers, rounded to
+// the storage type; step two (t+1 -> t+2) writes only the columns
+// [x0, x0 + ncols), lanes 2 .. ncols+1, so neighbouring strips overlap by
+// four columns of step-one work.  Rows: step two writes [y0, y0 + L); it needs
+// psi(t+1) on rows y0-1 .. y0+L, hence f*(t+1) on rows y0-2 .. y0+L+1, hence
+// psi(t) on rows y0-3 .. y0+L+2.  Step two pulls f*(t+1) from registers for
+// the x-unshifted directions (0, 2, 4) and from an LDS exchange row for the
+// six shifted ones, and runs three rows behind step one, so one row of the
+// march needs two barriers.  Both steps use the same arithmetic, in the same
+// order, as two single-step launches, so the result is bitwise identical.
+template <typename S, int NW, int PF>
+__device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restrict__ src,
+                                           typename Store<S>::E* __restrict__ dst,
+                                           const RunDev& d, int x0, int y0, int ncols, int nrows,
+                                           unsigned long long step,
+                                           unsigned long long* __restrict__ flag,
+                                           double (*ring1)[64 * NW + 2], double (*ring2)[64 * NW],
+                                           typename Store<S>::R (*xch)[64 * NW], double* haloL,
+                                           double* haloR) {
+  using T = Store<S>;
+  using R = typename T::R;
+  constexpr int SW = 64 * NW;
+  const int tid = threadIdx.x;
+  const int n1 = ncols + 4;                         // lanes that run step one
+  const bool act1 = tid < n1;
+  const bool out = tid >= 2 && tid < ncols + 2;     // lanes that write step two
+  auto wrapx = [&](int x) { return x < 0 ? x + d.nx : (x >= d.nx ? x - d.nx : x); };
+  auto wrapy = [&](int y) { return y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y); };
+  const Cols cx = cols_of(wrapx(x0 - 2 + (act1 ? tid : 0)), d.nx);
+  const int xl = wrapx(x0 - 3), xr = wrapx(x0 + ncols + 2);
+  const double rref = d.rho_ref;
+  bool bad1 = false, bad2 = false;
+  const int ya = y0 - 3;                            // first psi(t) row
+
+  // prologue: psi(t) of the two halo columns for rows y0-3 .. y0+nrows+2
+  for (int i = tid; i < 2 * (nrows + 6); i += SW) {
+    const int k = i >> 1;
+    R f[9];
+    pull9<S>(src, d, cols_of((i & 1) ? xr : xl, d.nx), wrapy(ya + k), f);
+    const double rho = rref + double(sum9(f));
+    ((i & 1) ? haloR : haloL)[k] = sqrt(psi2_of(rho, d));
+  }
+
+  // preload: psi(t) of rows y0-3 (ring slot 0) and y0-2 (slot 1); pulled row y0-2
+  R fc[9], fn[9];
+  double psi2c = 0.0;
+  if (act1) {
+    R f[9];
+    pull9<S>(src, d, cx, wrapy(ya), f);
+    pull9<S>(src, d, cx, wrapy(ya + 1), fc);
+    if (PF == 2) pull9<S>(src, d, cx, wrapy(ya + 2), fn);
+    ring1[0][tid + 1] = sqrt(psi2_of(rref + double(sum9(f)), d));
+    psi2c = psi2_of(rref + double(sum9(fc)), d);
+    ring1[1][tid + 1] = sqrt(psi2c);
+  }
+  __syncthreads();  // the halo columns are in LDS
+  if (tid == 0) {
+    ring1[0][0] = haloL[0];
+    ring1[0][n1 + 1] = haloR[0];
+    ring1[1][0] = haloL[1];
+    ring1[1][n1 + 1] = haloR[1];
+  }
+
+  // f*(t+1) of the last three step-one rows, kept for step two:
+  // gA = row y1-1 (all 9), gB = row y1-2 (0,1,3,2,5,6), gC = row y1-3 (2,5,6)
+  R gA[9], gB[6], gC[3];
+  R hp[9];          // step-two pulled populations of the row collided next
+  double psi2p = 0.0;
+  const int n_one = nrows + 4;                      // step-one rows y0-2 .. y0+nrows+1
+  for (int j = 0; j < n_one + 1; ++j) {
+    const int y1 = y0 - 2 + j;                      // step-one row collided at this j
+    // ---- phase 1: psi(t) of row y1+1; exchange of the rows step two pulls
+    R fnn[9];
+    double psi2n = 0.0;
+    if (j < n_one) {
+      const int sl = (j + 2) & 3;
+      if (act1) {
+        if (PF == 2) {
+          if (j + 1 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 2), fnn);
+        } else {
+          pull9<S>(src, d, cx, wrapy(y1 + 1), fn);
+        }
+        psi2n = psi2_of(rref + double(sum9(fn)), d);
+        ring1[sl][tid + 1] = sqrt(psi2n);
+      }
+      if (tid == 0) {
+        ring1[sl][0] = haloL[j + 2];
+        ring1[sl][n1 + 1] = haloR[j + 2];
+      }
+    }
+    if (j >= 3 && act1) {  // step two pulls row q = y1 - 2 below
+      xch[0][tid] = gB[1];
+      xch[1][tid] = gB[2];
+      xch[2][tid] = gC[1];
+      xch[3][tid] = gC[2];
+      xch[4][tid] = gA[7];
+      xch[5][tid] = gA[8];
+    }
+    __syncthreads();
+    // ---- phase 2: step-two pull of row q = y1-2 and its psi(t+1); step-one collide of row y1
+    const int q = y1 - 2;
+    R hn[9];
+    double psi2q = 0.0;
+    if (j >= 3 && tid >= 1 && tid < n1 - 1) {
+      hn[0] = gB[0];
+      hn[1] = xch[0][tid - 1];
+      hn[2] = gC[0];
+      hn[3] = xch[1][tid + 1];
+      hn[4] = gA[4];
+      hn[5] = xch[2][tid - 1];
+      hn[6] = xch[3][tid + 1];
+      hn[7] = xch[4][tid + 1];
+      hn[8] = xch[5][tid - 1];
+      psi2q = psi2_of(rref + double(sum9(hn)), d);
+      ring2[(q - (y0 - 1)) & 3][tid] = sqrt(psi2q);
+    }
+    if (j >= 1) {  // rotate the kept step-one rows (gA was produced at j-1)
+      gC[0] = gB[3]; gC[1] = gB[4]; gC[2] = gB[5];
+      gB[0] = gA[0]; gB[1] = gA[1]; gB[2] = gA[3];
+      gB[3] = gA[2]; gB[4] = gA[5]; gB[5] = gA[6];
+    }
+    if (j < n_one && act1) {
+      double Fx, Fy;
+      force3x3(ring1[j & 3], ring1[(j + 1) & 3], ring1[(j + 2) & 3], tid + 1, d.mG, Fx, Fy);
+      const R drho = sum9(fc);
+      const double rho64 = rref + double(drho);
+      if (out && y1 >= y0 && y1 < y0 + nrows) bad1 |= !(psi2c > 0.0) || !(rho64 > 0.0);
+      const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
+      collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) gA[a] = T::round(fc[a]);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) fc[a] = fn[a];
+      psi2c = psi2n;
+      if (PF == 2 && j + 1 < n_one) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) fn[a] = fnn[a];
+      }
+    }
+    __syncthreads();
+    // ---- phase 3: step-two collide of row r = q-1 and store
+    const int r = q - 1;
+    if (j >= 4 && out && r >= y0 && r < y0 + nrows) {
+      double Fx, Fy;
+      force3x3(ring2[(r - 1 - (y0 - 1)) & 3], ring2[(r - (y0 - 1)) & 3], ring2[(q - (y0 - 1)) & 3],
+               tid, d.mG, Fx, Fy);
+      const R drho = sum9(hp);
+      const double rho64 = rref + double(drho);
+      bad2 |= !(psi2p > 0.0) || !(rho64 > 0.0);
+      const R ip2 = d.sig != 0.0 ? rcp(R(psi2p)) : R(0);
+      collide<R>(hp, drho, R(rho64), mom_x(hp), mom_y(hp), R(Fx), R(Fy), ip2, d);
+      typename T::E* row = dst + (int64_t)wrapy(r) * d.pitch;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) T::st(row + a * d.plane + cx.x, hp[a]);
+    }
+    if (j >= 3) {
+#pragma unroll
+      for (int a = 0; a < 9; ++a) hp[a] = hn[a];
+      psi2p = psi2q;
+    }
+  }
+  // divergence: the first step that saw a bad node (one atomic per wave)
+  const auto b1 = __ballot(bad1), b2 = __ballot(bad2);
+  if (__lane_id() == 0 && (b1 | b2) != 0) atomicMin(flag, b1 != 0 ? step : step + 1);
+}
+
+// Two steps per launch over the single lattice; strips of at most 64*NW - 4
+// columns, spread evenly over nx; L as in k_step (0 = balanced schedule).
+template <typename S, int NW, int PF>
+__global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* __restrict__ src,
+                                                   typename Store<S>::E* __restrict__ dst,
+                                                   RunDev d, int L, int nstrips,
+                                                   const unsigned long long* stepbase,
+                                                   unsigned long long steplocal,
+                                                   unsigned long long* flag) {
+  using R = typename Store<S>::R;
+  __shared__ double ring1[4][64 * NW + 2];
+  __shared__ double ring2[4][64 * NW];
+  __shared__ R xch[6][64 * NW];
+  __shared__ double haloL[LMAX + 6], haloR[LMAX + 6];
+  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
+  if (*flag < step) return;  // diverged at an earlier step: the run is frozen
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  auto strip = [&](int sx, int& x0, int& nc) {
+    x0 = (int)((int64_t)sx * d.nx / nstrips);
+    nc = (int)((int64_t)(sx + 1) * d.nx / nstrips) - x0;
+  };
+  if (L > 0) {
+    const int sy = t / nstrips, sx = t - sy * nstrips;
+    int x0, nc;
+    strip(sx, x0, nc);
+    const int y0 = sy * L;
+    tile_step2<S, NW, PF>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2, xch,
+                          haloL, haloR);
+    return;
+  }
+  const int64_t total = (int64_t)nstrips * d.ny;
+  int64_t r = total * t / gridDim.x;
+  const int64_t e = total * (t + 1) / gridDim.x;
+  while (r < e) {
+    const int s = (int)(r / d.ny), y = (int)(r - (int64_t)s * d.ny);
+    int n = (int)min(e - r, (int64_t)(d.ny - y));
+    n = min(n, LMAX);
+    int x0, nc;
+    strip(s, x0, nc);
+    tile_step2<S, NW, PF>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, xch, haloL, haloR);
     r += n;
     __syncthreads();  // LDS is reused by the next piece
   }

@@ -33,10 +33,12 @@ constexpr unsigned long long kNoDiv = ~0ull;
   } while (0)
 
 // Launch shape of the step kernels: waves per block (strip of 64*nw columns),
-// rows per block (0 = balanced schedule over the resident grid) and the row
-// prefetch depth (1 or 2).
+// rows per block (0 = balanced schedule over the resident grid), the row
+// prefetch depth (1 or 2) and the time steps per launch (1, or 2 for the
+// two-step kernel of the single lattice).
 struct Tile {
   int nw, L, pf;
+  int ts = 1;
 };
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -249,9 +251,49 @@ hipError_t launch_step_s(const Tile& t, const void* src, void* dst, const RunDev
   }
 }
 
+template <typename S, int NW, int PF>
+hipError_t launch_step2_t(const void* src, void* dst, const RunDev& d, int L,
+                          const unsigned long long* base, unsigned long long local,
+                          unsigned long long* flag, hipStream_t st) {
+  const int SW = 64 * NW;
+  const int nstrips = (d.nx + SW - 5) / (SW - 4);  // strips of at most SW - 4 columns
+  int grid;
+  if (L > 0) {
+    grid = nstrips * ((d.ny + L - 1) / L);
+  } else {
+    const int64_t rows = (int64_t)nstrips * d.ny;
+    grid = resident_blocks((const void*)k_step2<S, NW, PF>, SW);
+    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, rows / 8));
+  }
+  using E = typename Store<S>::E;
+  hipLaunchKernelGGL((k_step2<S, NW, PF>), dim3(grid), dim3(SW), 0, st, static_cast<const E*>(src),
+                     static_cast<E*>(dst), d, L, nstrips, base, local, flag);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_step2_s(const Tile& t, const void* src, void* dst, const RunDev& d,
+                          const unsigned long long* base, unsigned long long local,
+                          unsigned long long* flag, hipStream_t st) {
+  switch (t.nw * 10 + t.pf) {
+    case 41: return launch_step2_t<S, 4, 1>(src, dst, d, t.L, base, local, flag, st);
+    case 42: return launch_step2_t<S, 4, 2>(src, dst, d, t.L, base, local, flag, st);
+    case 81: return launch_step2_t<S, 8, 1>(src, dst, d, t.L, base, local, flag, st);
+    default: return launch_step2_t<S, 8, 2>(src, dst, d, t.L, base, local, flag, st);
+  }
+}
+
+// One launch of the tile: t.ts time steps (1 or 2) from src into dst.
 hipError_t launch_step(int prec, const Tile& t, const void* src, void* dst, const RunDev& d,
                        const unsigned long long* base, unsigned long long local,
                        unsigned long long* flag, hipStream_t st) {
+  if (t.ts == 2) {
+    if (prec == LBM_PREC_F64) return launch_step2_s<double>(t, src, dst, d, base, local, flag, st);
+    if (prec == LBM_PREC_F32DEV) return launch_step2_s<float>(t, src, dst, d, base, local, flag, st);
+    if (prec == LBM_PREC_F32DEV_F64)
+      return launch_step2_s<f32s_f64a>(t, src, dst, d, base, local, flag, st);
+    return launch_step2_s<__half>(t, src, dst, d, base, local, flag, st);
+  }
   if (prec == LBM_PREC_F64) return launch_step_s<double>(t, src, dst, d, base, local, flag, st);
   if (prec == LBM_PREC_F32DEV) return launch_step_s<float>(t, src, dst, d, base, local, flag, st);
   if (prec == LBM_PREC_F32DEV_F64) return launch_step_s<f32s_f64a>(t, src, dst, d, base, local, flag, st);
@@ -391,17 +433,21 @@ size_t ctx_layout(const lbm_params& p, size_t* pop, size_t* aux, size_t* parts, 
   return 2 * *pop + *aux + *parts + *misc;
 }
 
-bool same_tile(const Tile& a, const Tile& b) { return a.nw == b.nw && a.L == b.L && a.pf == b.pf; }
+bool same_tile(const Tile& a, const Tile& b) {
+  return a.nw == b.nw && a.L == b.L && a.pf == b.pf && a.ts == b.ts;
+}
 
 // Strip widths of the single-lattice kernel (64 to 1024 columns) and of the
 // batched one (64 to 512 columns; batched lattices are at most a few hundred
 // columns wide).
 constexpr int kStepWaves[] = {1, 2, 4, 8, 16};
 constexpr int kBatchWaves[] = {1, 2, 4, 8};
+constexpr int kStep2Waves[] = {4, 8};  // two-step kernel: 252- and 508-column strips
 
-bool valid_tile(int nw, int L, int pf, int maxnw) {
+bool valid_tile(int nw, int L, int pf, int maxnw, int ts = 1) {
+  if (ts == 2 && nw != 4 && nw != 8) return false;
   return (nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16) && nw <= maxnw && L >= 0 &&
-         L <= LMAX && (pf == 1 || pf == 2);
+         L <= LMAX && (pf == 1 || pf == 2) && (ts == 1 || ts == 2);
 }
 
 void drop_graphs(lbm_ctx* c) {
@@ -428,10 +474,11 @@ int capture_graph(lbm_ctx* c, int parity) {
   hipGraph_t g;
   HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int i = 0; i < c->graph_k && e == hipSuccess; ++i) {
+  const int launches = c->graph_k / c->tile.ts;  // graph_k is even
+  for (int i = 0; i < launches && e == hipSuccess; ++i) {
     const int s = (parity + i) & 1;
     e = launch_step(c->p.precision, c->tile, c->buf[s], c->buf[s ^ 1], c->d, c->ctr,
-                    (unsigned long long)i, c->flag, c->st);
+                    (unsigned long long)i * c->tile.ts, c->flag, c->st);
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_counter_add, dim3(1), dim3(1), 0, c->st, c->ctr,
@@ -551,6 +598,12 @@ int lbm_init(const lbm_params* p, const double* rho0, const double* ux0, const d
     auto it = g_tune.find({p->nx, p->ny, p->precision, 0});
     if (it != g_tune.end()) c->tile = it->second;
   }
+  // the second buffer is written only at lattice nodes: clear its row padding once
+  // so that checkpoints of either buffer are deterministic
+  if (hipMemsetAsync(c->buf[1], 0, c->raw_bytes, c->st) != hipSuccess) {
+    delete c;
+    return LBM_EHIP;
+  }
   std::vector<char> raw;
   encode_any(p->precision, c->p, rref, f.data(), raw);
   st = upload_state(c, raw, 0);
@@ -575,16 +628,20 @@ int lbm_step(lbm_ctx* c, int64_t n) {
         if (st != LBM_OK) return st;
       }
       HIPCHK(hipGraphLaunch(c->gexec[c->cur], c->st));
-      done += c->graph_k;  // k is even: parity unchanged
+      done += c->graph_k;
       c->step += c->graph_k;
+      c->cur ^= (c->graph_k / c->tile.ts) & 1;  // one buffer swap per launch
     }
   }
-  for (; done < n; ++done) {
+  while (done < n) {
     const int s = c->cur;
-    HIPCHK(launch_step(c->p.precision, c->tile, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
+    Tile t = c->tile;
+    if (n - done < t.ts) t.ts = 1;  // odd remainder of a two-step tile: one single step
+    HIPCHK(launch_step(c->p.precision, t, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
                        (unsigned long long)c->step, c->flag, c->st));
     c->cur ^= 1;
-    c->step += 1;
+    c->step += t.ts;
+    done += t.ts;
   }
   return LBM_OK;
 }
@@ -720,46 +777,54 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
   return upload_state(c, raw, h.step);
 }
 
-int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth) {
-  if (!c || !valid_tile(nw, L, depth, 16)) return LBM_EINVAL;
-  c->tile = Tile{nw, L, depth};
+int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
+  if (!c || !valid_tile(nw, L, depth, 16, steps)) return LBM_EINVAL;
+  c->tile = Tile{nw, L, depth, steps};
   return LBM_OK;
 }
 
-int lbm_get_tile(lbm_ctx* c, int32_t* nw, int32_t* L, int32_t* depth) {
+int lbm_get_tile(lbm_ctx* c, int32_t* nw, int32_t* L, int32_t* depth, int32_t* steps) {
   if (!c) return LBM_EINVAL;
   if (nw) *nw = c->tile.nw;
   if (L) *L = c->tile.L;
   if (depth) *depth = c->tile.pf;
+  if (steps) *steps = c->tile.ts;
   return LBM_OK;
 }
 
-int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out) {
+int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, int32_t* steps_out) {
   if (!c) return LBM_EINVAL;
   float best = 1e30f;
   Tile bt = c->tile;
   const int s = c->cur;
   const int64_t nodes = (int64_t)c->p.nx * c->p.ny;
   const int reps = nodes >= (1 << 22) ? 3 : 10;
+  std::vector<Tile> cand;
   for (int nw : kStepWaves) {
     if (nw > 1 && 64 * (nw / 2) >= c->p.nx) continue;
     for (int pf : {1, 2})
-      for (int L : {0, 4, 8, 16, 32, 64, 128}) {
-        if (L > 2 * c->p.ny) continue;
-        const Tile t{nw, L, pf};
-        const float ms = time_launches(
-            c->st,
-            [&] {
-              return launch_step(c->p.precision, t, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
-                                 (unsigned long long)c->step, c->flag, c->st);
-            },
-            reps);
-        if (ms < 0) return LBM_EHIP;
-        if (ms < best) {
-          best = ms;
-          bt = t;
-        }
-      }
+      for (int L : {0, 4, 8, 16, 32, 64, 128})
+        if (L <= 2 * c->p.ny) cand.push_back(Tile{nw, L, pf, 1});
+  }
+  for (int nw : kStep2Waves) {
+    if (nw > 4 && 64 * (nw / 2) >= c->p.nx) continue;
+    for (int pf : {1, 2})
+      for (int L : {0, 32, 64, 128})
+        if (L <= 2 * c->p.ny) cand.push_back(Tile{nw, L, pf, 2});
+  }
+  for (const Tile& t : cand) {
+    const float ms = time_launches(
+        c->st,
+        [&] {
+          return launch_step(c->p.precision, t, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
+                             (unsigned long long)c->step, c->flag, c->st);
+        },
+        reps);
+    if (ms < 0) return LBM_EHIP;
+    if (ms / t.ts < best) {  // time per lattice step
+      best = ms / t.ts;
+      bt = t;
+    }
   }
   c->tile = bt;
   {
@@ -769,6 +834,7 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out) {
   if (nw_out) *nw_out = bt.nw;
   if (L_out) *L_out = bt.L;
   if (depth_out) *depth_out = bt.pf;
+  if (steps_out) *steps_out = bt.ts;
   return LBM_OK;
 }
 
@@ -1002,6 +1068,7 @@ int lbm_batch_init(int32_t n, const lbm_params* p, const double* const* rho0, vo
     return st;
   }
   hipError_t e = hipMemcpyAsync(b->buf[0], pool.data(), pool.size(), hipMemcpyHostToDevice, b->st);
+  if (e == hipSuccess) e = hipMemsetAsync(b->buf[1], 0, pool.size(), b->st);  // row padding
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_runs, b->d.data(), n * sizeof(RunDev), hipMemcpyHostToDevice, b->st);
   std::vector<unsigned long long> fl(n + 1, kNoDiv);

@@ -246,17 +246,18 @@ class Lattice:
 
     # -- launch shape
     def tune(self):
-        w, r, d = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(lib().lbm_tune(self.ctx, C.byref(w), C.byref(r), C.byref(d)), "lbm_tune")
-        return w.value, r.value, d.value
+        """Fastest tile per lattice step: (waves, rows, depth, steps per launch)."""
+        w, r, d, k = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbm_tune(self.ctx, C.byref(w), C.byref(r), C.byref(d), C.byref(k)), "lbm_tune")
+        return w.value, r.value, d.value, k.value
 
-    def set_tile(self, waves: int, rows: int, depth: int = 2):
-        _check(lib().lbm_set_tile(self.ctx, int(waves), int(rows), int(depth)), "lbm_set_tile")
+    def set_tile(self, waves: int, rows: int, depth: int = 2, steps: int = 1):
+        _check(lib().lbm_set_tile(self.ctx, int(waves), int(rows), int(depth), int(steps)), "lbm_set_tile")
 
     def get_tile(self):
-        w, r, d = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(lib().lbm_get_tile(self.ctx, C.byref(w), C.byref(r), C.byref(d)), "lbm_get_tile")
-        return w.value, r.value, d.value
+        w, r, d, k = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbm_get_tile(self.ctx, C.byref(w), C.byref(r), C.byref(d), C.byref(k)), "lbm_get_tile")
+        return w.value, r.value, d.value, k.value
 
     def set_graph_steps(self, k: int):
         _check(lib().lbm_set_graph_steps(self.ctx, int(k)), "lbm_set_graph_steps")

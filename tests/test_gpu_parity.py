@@ -104,7 +104,9 @@ def test_tile_shapes_bitwise_identical(L):
     rho0 = slab_rho(200, 90, CS, 0.8, seed=3)
     outs = []
     for tile in [(1, 4, 1), (1, 16, 2), (2, 8, 1), (4, 128, 2), (4, 5, 2), (2, 33, 1), (1, 0, 2),
-                 (4, 0, 1), (2, 0, 2), (8, 0, 2), (16, 7, 1)]:
+                 (4, 0, 1), (2, 0, 2), (8, 0, 2), (16, 7, 1),
+                 # two steps per launch (37 steps: 18 launches and one single step)
+                 (4, 0, 2, 2), (4, 5, 1, 2), (8, 16, 2, 2), (8, 128, 1, 2), (4, 33, 2, 2)]:
         lat = L.Lattice(gp, rho0)
         lat.set_tile(*tile)
         lat.step(37)
@@ -120,7 +122,8 @@ def test_wide_strips_bitwise_identical(L):
     gp, op = pair(L, 1100, 40, t=0.8, tau=0.9, scheme=2, sigma=0.1)
     rho0 = slab_rho(1100, 40, CS, 0.8, seed=4)
     outs = []
-    for tile in [(1, 8, 1), (8, 0, 2), (8, 16, 1), (16, 0, 2), (16, 5, 1), (4, 0, 2)]:
+    for tile in [(1, 8, 1), (8, 0, 2), (8, 16, 1), (16, 0, 2), (16, 5, 1), (4, 0, 2),
+                 (4, 0, 2, 2), (8, 0, 1, 2), (8, 7, 2, 2)]:
         lat = L.Lattice(gp, rho0)
         lat.set_tile(*tile)
         lat.step(21)
@@ -131,6 +134,58 @@ def test_wide_strips_bitwise_identical(L):
     f = olbm.init_equilibrium(rho0)
     assert olbm.step(op, f, 21)[0] == 0
     assert rel_err(outs[0], f) < TOL64
+
+
+@pytest.mark.parametrize("k", [10, 12])
+def test_two_step_graph_replay_bitwise(L, k):
+    # graphs of k steps = k/2 two-step launches (odd for k = 10: the buffer parity flips
+    # per replay), an odd eager head and tail, against single steps
+    gp, _ = pair(L, 300, 70, t=0.8, tau=0.8, scheme=2, sigma=0.105)
+    rho0 = slab_rho(300, 70, CS, 0.8, seed=6)
+    a = L.Lattice(gp, rho0)
+    a.set_tile(2, 8, 1)
+    a.step(3 + 4 * k + 5)
+    fa = a.get_populations()[0]
+    b = L.Lattice(gp, rho0)
+    b.set_tile(4, 0, 2, 2)
+    b.set_graph_steps(k)
+    b.step(3)
+    b.step(2 * k)
+    b.step(2 * k + 5)
+    assert b.status()[1] == 3 + 4 * k + 5
+    assert np.array_equal(b.get_populations()[0], fa)
+    a.close(); b.close()
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (5, 4), (130, 7), (260, 5)])
+def test_two_step_edge_shapes(L, shape):
+    nx, ny = shape
+    gp, op = pair(L, nx, ny, t=0.9, tau=0.9, scheme=2, sigma=0.05)
+    rng = np.random.default_rng(nx * 1000 + ny)
+    rho0 = np.ascontiguousarray(0.1 + 0.02 * rng.random((ny, nx)))
+    errs, _, _ = _run_both(L, gp, op, rho0, [2, 25], tile=(4, 0, 2, 2))
+    assert max(errs) < TOL64, errs
+
+
+def test_two_step_divergence_step(L):
+    # the same divergence as test_divergence_step_matches_oracle, through two-step launches:
+    # the step reported is the first one with a bad node, whichever half of a launch it is
+    gp, op = pair(L, 96, 80, t=0.6, tau=1.0, scheme=2, sigma=0.105, eos=PR)
+    from oracle import thermo as th
+    import synth
+    c = th.maxwell_pr(0.6)
+    rho0 = synth.droplet(96, 80, c.rho_l, c.rho_g, 20, 4.0, 0.005)
+    f = olbm.init_equilibrium(rho0)
+    st_o, d_o = olbm.step(op, f, 200)
+    one = L.Lattice(gp, rho0)
+    one.step(200)
+    two = L.Lattice(gp, rho0)
+    two.set_tile(4, 16, 2, 2)
+    two.step(200)
+    assert st_o == olbm.EDIVERGED
+    assert one.status()[2] == two.status()[2]
+    assert abs(two.status()[2] - d_o) <= 2
+    one.close(); two.close()
 
 
 def test_graph_replay_bitwise(L):
