@@ -385,68 +385,55 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
 // ---- two time steps per launch ------------------------------------------------
 //
 // The populations cross HBM once per two steps.  Lane i of a block owns
-// column c = x0 - 2 + i for both steps.  Step one (t -> t+1) runs on every
-// lane exactly as tile_step does and leaves f*(t+1) in registers, rounded to
-// the storage type; step two (t+1 -> t+2) writes only the columns
-// [x0, x0 + ncols), lanes 2 .. ncols+1, so neighbouring strips overlap by
-// four columns of step-one work.  Rows: step two writes [y0, y0 + L); it needs
-// psi(t+1) on rows y0-1 .. y0+L, hence f*(t+1) on rows y0-2 .. y0+L+1, hence
-// psi(t) on rows y0-3 .. y0+L+2.  Step two pulls f*(t+1) from registers for
-// the x-unshifted directions (0, 2, 4) and from an LDS exchange row for the
-// six shifted ones, and runs three rows behind step one, so one row of the
-// march needs two barriers.  Both steps use the same arithmetic, in the same
-// order, as two single-step launches, so the result is bitwise identical.
+// column c = x0 - 3 + i for both steps, i < ncols + 6:
+//   * every lane pulls its column and evaluates psi(t);
+//   * lanes 1 .. ncols+4 run step one (t -> t+1) exactly as tile_step does and
+//     keep f*(t+1) in registers, rounded to the storage type;
+//   * lanes 2 .. ncols+3 pull f*(t+1) for step two and evaluate psi(t+1);
+//   * lanes 3 .. ncols+2 finish step two and write the columns [x0, x0+ncols),
+// so neighbouring strips overlap by six columns of recomputed work and no
+// halo column is loaded apart from the coalesced row loads.  Rows: step two
+// writes [y0, y0 + L); it needs psi(t+1) on rows y0-1 .. y0+L, hence f*(t+1)
+// on rows y0-2 .. y0+L+1, hence psi(t) on rows y0-3 .. y0+L+2.  Step two
+// pulls f*(t+1) from registers for the x-unshifted directions (0, 2, 4) and
+// from an LDS exchange row for the six shifted ones, and runs three rows
+// behind step one; one row of the march takes two barriers.  Both steps use
+// the same arithmetic, in the same order, as two single-step launches, so the
+// result is bitwise identical.
 template <typename S, int NW, int PF>
 __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restrict__ src,
                                            typename Store<S>::E* __restrict__ dst,
                                            const RunDev& d, int x0, int y0, int ncols, int nrows,
                                            unsigned long long step,
                                            unsigned long long* __restrict__ flag,
-                                           double (*ring1)[64 * NW + 2], double (*ring2)[64 * NW],
-                                           typename Store<S>::R (*xch)[64 * NW], double* haloL,
-                                           double* haloR) {
+                                           double (*ring1)[64 * NW], double (*ring2)[64 * NW],
+                                           typename Store<S>::R (*xch)[64 * NW]) {
   using T = Store<S>;
   using R = typename T::R;
-  constexpr int SW = 64 * NW;
   const int tid = threadIdx.x;
-  const int n1 = ncols + 4;                         // lanes that run step one
-  const bool act1 = tid < n1;
-  const bool out = tid >= 2 && tid < ncols + 2;     // lanes that write step two
+  const int n0 = ncols + 6;                         // lanes that evaluate psi(t)
+  const bool act0 = tid < n0;
+  const bool act1 = tid >= 1 && tid < n0 - 1;       // lanes that run step one
+  const bool pull2 = tid >= 2 && tid < n0 - 2;      // lanes that pull for step two
+  const bool out = tid >= 3 && tid < ncols + 3;     // lanes that write step two
   auto wrapx = [&](int x) { return x < 0 ? x + d.nx : (x >= d.nx ? x - d.nx : x); };
   auto wrapy = [&](int y) { return y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y); };
-  const Cols cx = cols_of(wrapx(x0 - 2 + (act1 ? tid : 0)), d.nx);
-  const int xl = wrapx(x0 - 3), xr = wrapx(x0 + ncols + 2);
+  const Cols cx = cols_of(wrapx(x0 - 3 + (act0 ? tid : 0)), d.nx);
   const double rref = d.rho_ref;
   bool bad1 = false, bad2 = false;
   const int ya = y0 - 3;                            // first psi(t) row
 
-  // prologue: psi(t) of the two halo columns for rows y0-3 .. y0+nrows+2
-  for (int i = tid; i < 2 * (nrows + 6); i += SW) {
-    const int k = i >> 1;
-    R f[9];
-    pull9<S>(src, d, cols_of((i & 1) ? xr : xl, d.nx), wrapy(ya + k), f);
-    const double rho = rref + double(sum9(f));
-    ((i & 1) ? haloR : haloL)[k] = sqrt(psi2_of(rho, d));
-  }
-
   // preload: psi(t) of rows y0-3 (ring slot 0) and y0-2 (slot 1); pulled row y0-2
   R fc[9], fn[9];
   double psi2c = 0.0;
-  if (act1) {
+  if (act0) {
     R f[9];
     pull9<S>(src, d, cx, wrapy(ya), f);
     pull9<S>(src, d, cx, wrapy(ya + 1), fc);
     if (PF == 2) pull9<S>(src, d, cx, wrapy(ya + 2), fn);
-    ring1[0][tid + 1] = sqrt(psi2_of(rref + double(sum9(f)), d));
+    ring1[0][tid] = sqrt(psi2_of(rref + double(sum9(f)), d));
     psi2c = psi2_of(rref + double(sum9(fc)), d);
-    ring1[1][tid + 1] = sqrt(psi2c);
-  }
-  __syncthreads();  // the halo columns are in LDS
-  if (tid == 0) {
-    ring1[0][0] = haloL[0];
-    ring1[0][n1 + 1] = haloR[0];
-    ring1[1][0] = haloL[1];
-    ring1[1][n1 + 1] = haloR[1];
+    ring1[1][tid] = sqrt(psi2c);
   }
 
   // f*(t+1) of the last three step-one rows, kept for step two:
@@ -460,21 +447,14 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
     // ---- phase 1: psi(t) of row y1+1; exchange of the rows step two pulls
     R fnn[9];
     double psi2n = 0.0;
-    if (j < n_one) {
-      const int sl = (j + 2) & 3;
-      if (act1) {
-        if (PF == 2) {
-          if (j + 1 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 2), fnn);
-        } else {
-          pull9<S>(src, d, cx, wrapy(y1 + 1), fn);
-        }
-        psi2n = psi2_of(rref + double(sum9(fn)), d);
-        ring1[sl][tid + 1] = sqrt(psi2n);
+    if (j < n_one && act0) {
+      if (PF == 2) {
+        if (j + 1 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 2), fnn);
+      } else {
+        pull9<S>(src, d, cx, wrapy(y1 + 1), fn);
       }
-      if (tid == 0) {
-        ring1[sl][0] = haloL[j + 2];
-        ring1[sl][n1 + 1] = haloR[j + 2];
-      }
+      psi2n = psi2_of(rref + double(sum9(fn)), d);
+      ring1[(j + 2) & 3][tid] = sqrt(psi2n);
     }
     if (j >= 3 && act1) {  // step two pulls row q = y1 - 2 below
       xch[0][tid] = gB[1];
@@ -489,7 +469,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
     const int q = y1 - 2;
     R hn[9];
     double psi2q = 0.0;
-    if (j >= 3 && tid >= 1 && tid < n1 - 1) {
+    if (j >= 3 && pull2) {
       hn[0] = gB[0];
       hn[1] = xch[0][tid - 1];
       hn[2] = gC[0];
@@ -507,16 +487,18 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
       gB[0] = gA[0]; gB[1] = gA[1]; gB[2] = gA[3];
       gB[3] = gA[2]; gB[4] = gA[5]; gB[5] = gA[6];
     }
-    if (j < n_one && act1) {
-      double Fx, Fy;
-      force3x3(ring1[j & 3], ring1[(j + 1) & 3], ring1[(j + 2) & 3], tid + 1, d.mG, Fx, Fy);
-      const R drho = sum9(fc);
-      const double rho64 = rref + double(drho);
-      if (out && y1 >= y0 && y1 < y0 + nrows) bad1 |= !(psi2c > 0.0) || !(rho64 > 0.0);
-      const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
-      collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
+    if (j < n_one && act0) {
+      if (act1) {
+        double Fx, Fy;
+        force3x3(ring1[j & 3], ring1[(j + 1) & 3], ring1[(j + 2) & 3], tid, d.mG, Fx, Fy);
+        const R drho = sum9(fc);
+        const double rho64 = rref + double(drho);
+        if (out && y1 >= y0 && y1 < y0 + nrows) bad1 |= !(psi2c > 0.0) || !(rho64 > 0.0);
+        const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
+        collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
 #pragma unroll
-      for (int a = 0; a < 9; ++a) gA[a] = T::round(fc[a]);
+        for (int a = 0; a < 9; ++a) gA[a] = T::round(fc[a]);
+      }
 #pragma unroll
       for (int a = 0; a < 9; ++a) fc[a] = fn[a];
       psi2c = psi2n;
@@ -552,8 +534,10 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   if (__lane_id() == 0 && (b1 | b2) != 0) atomicMin(flag, b1 != 0 ? step : step + 1);
 }
 
-// Two steps per launch over the single lattice; strips of at most 64*NW - 4
-// columns, spread evenly over nx; L as in k_step (0 = balanced schedule).
+// Two steps per launch over the single lattice; strips of at most 64*NW - 6
+// columns, spread evenly over nx.  L > 0: one block per (strip, L-row chunk);
+// L == 0: balanced schedule, every block marches one contiguous share of the
+// strip-major row space (no length cap: the tile holds no per-row arrays).
 template <typename S, int NW, int PF>
 __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* __restrict__ src,
                                                    typename Store<S>::E* __restrict__ dst,
@@ -562,10 +546,9 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
                                                    unsigned long long steplocal,
                                                    unsigned long long* flag) {
   using R = typename Store<S>::R;
-  __shared__ double ring1[4][64 * NW + 2];
+  __shared__ double ring1[4][64 * NW];
   __shared__ double ring2[4][64 * NW];
   __shared__ R xch[6][64 * NW];
-  __shared__ double haloL[LMAX + 6], haloR[LMAX + 6];
   const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
   if (*flag < step) return;  // diverged at an earlier step: the run is frozen
   const int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -578,8 +561,7 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
     int x0, nc;
     strip(sx, x0, nc);
     const int y0 = sy * L;
-    tile_step2<S, NW, PF>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2, xch,
-                          haloL, haloR);
+    tile_step2<S, NW, PF>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2, xch);
     return;
   }
   const int64_t total = (int64_t)nstrips * d.ny;
@@ -587,11 +569,10 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
   const int64_t e = total * (t + 1) / gridDim.x;
   while (r < e) {
     const int s = (int)(r / d.ny), y = (int)(r - (int64_t)s * d.ny);
-    int n = (int)min(e - r, (int64_t)(d.ny - y));
-    n = min(n, LMAX);
+    const int n = (int)min(e - r, (int64_t)(d.ny - y));
     int x0, nc;
     strip(s, x0, nc);
-    tile_step2<S, NW, PF>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, xch, haloL, haloR);
+    tile_step2<S, NW, PF>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, xch);
     r += n;
     __syncthreads();  // LDS is reused by the next piece
   }

@@ -256,7 +256,7 @@ hipError_t launch_step2_t(const void* src, void* dst, const RunDev& d, int L,
                           const unsigned long long* base, unsigned long long local,
                           unsigned long long* flag, hipStream_t st) {
   const int SW = 64 * NW;
-  const int nstrips = (d.nx + SW - 5) / (SW - 4);  // strips of at most SW - 4 columns
+  const int nstrips = (d.nx + SW - 7) / (SW - 6);  // strips of at most SW - 6 columns
   int grid;
   if (L > 0) {
     grid = nstrips * ((d.ny + L - 1) / L);
@@ -442,7 +442,7 @@ bool same_tile(const Tile& a, const Tile& b) {
 // columns wide).
 constexpr int kStepWaves[] = {1, 2, 4, 8, 16};
 constexpr int kBatchWaves[] = {1, 2, 4, 8};
-constexpr int kStep2Waves[] = {4, 8};  // two-step kernel: 252- and 508-column strips
+constexpr int kStep2Waves[] = {4, 8};  // two-step kernel: 250- and 506-column strips
 
 bool valid_tile(int nw, int L, int pf, int maxnw, int ts = 1) {
   if (ts == 2 && nw != 4 && nw != 8) return false;
