@@ -1,7 +1,9 @@
-"""The learned sigma proposal, end to end on the GPU at reduced scale: batched
-flat-interface runs -> network trained by the library's kernels -> proposed
-sigma -> FP64 lattice verification, compared with the method without the
-network (the paper's fixed sigma = 0.105, the theory sigma*, LB bisection)."""
+"""The learned sigma proposal, end to end on the GPU at the configured scale:
+10,240 batched flat-interface runs of 30,000 steps -> network trained by the
+library's kernels (80/20 split) -> proposed sigma for 32 held-out (T/Tc, tau)
+pairs -> FP64 256 x 32 lattice verification of 30,000 steps, compared with the
+method without the network (the paper's fixed sigma = 0.105, the theory sigma*,
+LB bisection)."""
 import json
 import os
 
@@ -23,24 +25,24 @@ def S():
 
 @pytest.fixture(scope="module")
 def trained(S):
-    X, Y, info = S.dataset(1024, steps=20000, batch=256, log=print)
+    X, Y, info = S.dataset(10240, steps=30000, batch=256, log=print)
     print("dataset", info, X.shape)
-    assert X.shape[0] >= 500, info
-    net, rep = S.fit(X, Y, steps=8000, lr=3e-3, batch=256)
+    assert X.shape[0] >= 8000, info
+    net, rep = S.fit(X, Y, steps=20000, lr=3e-3, batch=1024)
     print("surrogate fit:", {k: v for k, v in rep.items() if k != "loss_history"})
-    # held-out runs span rho_g over three decades (T/Tc 0.5 .. 0.95); at this reduced
-    # scale (1024 runs) the median error stays within 2 %; the verification decides
-    assert max(rep["heldout_rel_err_median"]) < 0.02, rep
+    # held-out runs span rho_g over three decades (T/Tc 0.5 .. 0.95): median error within
+    # 1 % (measured 0.07 % for rho_l, 0.5 % for rho_g); the lattice verification decides
+    assert max(rep["heldout_rel_err_median"]) < 0.01, rep
     return net
 
 
 def test_surrogate_gains_over_fixed_and_theory_sigma(S, trained):
-    pairs = S.heldout_pairs(8)
+    pairs = S.heldout_pairs(32)
     g = json.load(open(GOLD))
     theory = [float(np.interp(t, g["t_over_tc"], g["sigma_star"])) for t, _ in pairs]
-    sig, e_net, runs = S.propose_and_verify(trained, pairs, steps=20000, tol=0.01, bisect_iters=8)
-    e_fix, _ = S.verify(pairs, [0.105] * len(pairs), steps=20000)
-    e_th, _ = S.verify(pairs, theory, steps=20000)
+    sig, e_net, runs = S.propose_and_verify(trained, pairs, steps=30000, tol=0.01, bisect_iters=8)
+    e_fix, _ = S.verify(pairs, [0.105] * len(pairs), steps=30000)
+    e_th, _ = S.verify(pairs, theory, steps=30000)
     worst = lambda e: np.max(e, axis=1)
     print("pairs", [(round(a, 3), round(b, 3)) for a, b in pairs])
     print("sigma: net", np.round(sig, 4), "theory", np.round(theory, 4), "lattice runs", runs)
@@ -55,8 +57,8 @@ def test_surrogate_gains_over_fixed_and_theory_sigma(S, trained):
 
 def test_bisection_baseline(S):
     pairs = S.heldout_pairs(4, seed=99)
-    sig_b, nruns_b = S.bisect_sigma(pairs, steps=20000, iters=8)
-    e_b, _ = S.verify(pairs, sig_b, steps=20000)
+    sig_b, nruns_b = S.bisect_sigma(pairs, steps=30000, iters=8)
+    e_b, _ = S.verify(pairs, sig_b, steps=30000)
     print("bisection sigma", np.round(sig_b, 4), "errors", np.round(np.max(e_b, 1), 4))
     assert nruns_b == 8 * len(pairs)
     assert np.all(np.max(e_b, 1) < 0.01)
