@@ -184,24 +184,27 @@ __device__ __forceinline__ void force3x3(const double* rs, const double* rc, con
   Fy = c * Sy;
 }
 
-// e_a . (x, y) for the D2Q9 directions (components 0 or +-1: adds only).
+// BGK collision with the forcing scheme in general form (see RunDev).
+//
+// For direction a the update is s_a + om (seq_a - s_a) + F_a with
+//   seq_a = w (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u))        (Eq. 2, deviation form)
+//   F_a   = w [3 B_e e.F + C_e (9 (e.v)(e.F) - 3 v.F)]             (Eq. 12)
+// The opposite direction (e -> -e) flips the odd terms only, so each pair is
+// evaluated once: seq = A +- B, F_a = C +- D, and s' = (s - om s) + (P +- Q) with
+// P = om A + C, Q = om B + D.
 template <typename R>
-__device__ __forceinline__ R edot(int a, R x, R y) {
+__device__ __forceinline__ void collide_pair(R& sa, R& sb, R eu, R eF, R ev, R w, R wr3, R wCe,
+                                             R wBe3, R rho, R drho, R usq, R vF3, R om) {
 #pragma clang fp contract(off)
-  switch (a) {
-    case 1: return x;
-    case 2: return y;
-    case 3: return -x;
-    case 4: return -y;
-    case 5: return x + y;
-    case 6: return y - x;
-    case 7: return -(x + y);
-    case 8: return x - y;
-    default: return R(0);
-  }
+  const R A = w * fma(rho, fma(R(4.5) * eu, eu, -usq), drho);
+  const R B = wr3 * eu;
+  const R C = wCe * fma(R(9) * ev, eF, -vF3);
+  const R D = wBe3 * eF;
+  const R P = fma(om, A, C), Q = fma(om, B, D);
+  sa = fma(-om, sa, sa) + (P + Q);
+  sb = fma(-om, sb, sb) + (P - Q);
 }
 
-// BGK collision with the forcing scheme in general form (see RunDev).
 template <typename R>
 __device__ __forceinline__ void collide(R (&s)[9], R drho, R rho, R jx, R jy, R Fx, R Fy,
                                         R inv_psi2, const RunDev& d) {
@@ -215,16 +218,22 @@ __device__ __forceinline__ void collide(R (&s)[9], R drho, R rho, R jx, R jy, R 
   const R om = R(d.inv_tau), Be3 = R(3.0 * d.Be), Ce = R(d.Ce);
   const R usq = R(1.5) * fma(wx, wx, wy * wy);
   const R vF3 = R(3) * fma(vx, Fx, vy * Fy);
-#pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    const R w = R(kW[a]);
-    const R eu = edot(a, wx, wy), eF = edot(a, Fx, Fy), ev = edot(a, vx, vy);
-    // f_eq deviation w (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)), Eq. (2)
-    const R seq = w * fma(rho, fma(R(4.5) * eu, eu, fma(R(3), eu, -usq)), drho);
-    // forcing term w [3 B_e e.F + C_e (9 (e.v)(e.F) - 3 v.F)], Eq. (12)
-    const R Fa = w * fma(Be3, eF, Ce * fma(R(9) * ev, eF, -vF3));
-    s[a] = fma(om, seq - s[a], s[a]) + Fa;
+  const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
+  const R rho3 = R(3) * rho;
+  const R wr3_1 = w1 * rho3, wCe1 = w1 * Ce, wBe3_1 = w1 * Be3;
+  const R wr3_2 = w2 * rho3, wCe2 = w2 * Ce, wBe3_2 = w2 * Be3;
+  // rest direction: e = 0
+  {
+    const R A0 = w0 * fma(rho, -usq, drho);
+    const R C0 = (w0 * Ce) * -vF3;
+    s[0] = fma(-om, s[0], s[0]) + fma(om, A0, C0);
   }
+  // axis pairs (e1, e3 = -e1), (e2, e4 = -e2)
+  collide_pair(s[1], s[3], wx, Fx, vx, w1, wr3_1, wCe1, wBe3_1, rho, drho, usq, vF3, om);
+  collide_pair(s[2], s[4], wy, Fy, vy, w1, wr3_1, wCe1, wBe3_1, rho, drho, usq, vF3, om);
+  // diagonal pairs (e5 = (1,1), e7 = -e5), (e6 = (-1,1), e8 = -e6)
+  collide_pair(s[5], s[7], wx + wy, Fx + Fy, vx + vy, w2, wr3_2, wCe2, wBe3_2, rho, drho, usq, vF3, om);
+  collide_pair(s[6], s[8], wy - wx, Fy - Fx, vy - vx, w2, wr3_2, wCe2, wBe3_2, rho, drho, usq, vF3, om);
 }
 
 template <typename R>
