@@ -42,6 +42,9 @@ struct RunDev {
   // forcing scheme in general form: u_eq = u + c_eq F/rho,
   // F_a = w_a [3 Be e.F + Ce (9 (e.vf)(e.F) - 3 vf.F)], vf = u + c_f F/rho + sig F/psi^2
   double c_eq, c_f, sig, Be, Ce;
+  // products used by the collision: w0 Ce, w1 Ce, w2 Ce and 3 w1 Be, 3 w2 Be
+  // (w0, w1, w2 = 4/9, 1/9, 1/36)
+  double wCe0, wCe1, wCe2, wBe3_1, wBe3_2;
   double rho_ref;           // deviation reference density (0 for FP64 storage)
   int32_t run, pad;
 };
@@ -215,17 +218,16 @@ __device__ __forceinline__ void collide(R (&s)[9], R drho, R rho, R jx, R jy, R 
   const R wx = fma(R(d.c_eq), Fr_x, ux), wy = fma(R(d.c_eq), Fr_y, uy);
   const R sg = R(d.sig) * inv_psi2;
   const R vx = fma(sg, Fx, fma(R(d.c_f), Fr_x, ux)), vy = fma(sg, Fy, fma(R(d.c_f), Fr_y, uy));
-  const R om = R(d.inv_tau), Be3 = R(3.0 * d.Be), Ce = R(d.Ce);
+  const R om = R(d.inv_tau);
   const R usq = R(1.5) * fma(wx, wx, wy * wy);
   const R vF3 = R(3) * fma(vx, Fx, vy * Fy);
   const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
-  const R rho3 = R(3) * rho;
-  const R wr3_1 = w1 * rho3, wCe1 = w1 * Ce, wBe3_1 = w1 * Be3;
-  const R wr3_2 = w2 * rho3, wCe2 = w2 * Ce, wBe3_2 = w2 * Be3;
+  const R wr3_1 = R(3.0 / 9.0) * rho, wr3_2 = R(3.0 / 36.0) * rho;
+  const R wCe1 = R(d.wCe1), wBe3_1 = R(d.wBe3_1), wCe2 = R(d.wCe2), wBe3_2 = R(d.wBe3_2);
   // rest direction: e = 0
   {
     const R A0 = w0 * fma(rho, -usq, drho);
-    const R C0 = (w0 * Ce) * -vF3;
+    const R C0 = R(d.wCe0) * -vF3;
     s[0] = fma(-om, s[0], s[0]) + fma(om, A0, C0);
   }
   // axis pairs (e1, e3 = -e1), (e2, e4 = -e2)

@@ -127,6 +127,11 @@ RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64
       d.Be = d.Ce = 1.0 - 0.5 / p.tau;
       break;
   }
+  d.wCe0 = 4.0 / 9.0 * d.Ce;
+  d.wCe1 = 1.0 / 9.0 * d.Ce;
+  d.wCe2 = 1.0 / 36.0 * d.Ce;
+  d.wBe3_1 = 3.0 / 9.0 * d.Be;
+  d.wBe3_2 = 3.0 / 36.0 * d.Be;
   d.rho_ref = rho_ref;
   d.run = run;
   return d;
