@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="batched,precision,droplet1024",
+    ap.add_argument("--legs", default="batched,precision,droplet1024,slab64",
                     help="comma-separated extra legs, or 'none'")
     ap.add_argument("--batch-steps", type=int, default=30000,
                     help="steps of the batched FP32-vs-FP64 coexistence comparison")
@@ -196,6 +196,9 @@ def main():
         log(f"droplet1024 leg: {d}")
         out["droplet1024"] = dict(d, note="1024^2 Peng-Robinson droplet r=128, tau=1, improved "
                                           "sigma=0.105; at 0.6 Tc the run leaves the EOS range")
+    if "slab64" in legs:
+        out["slab64"] = slab64_leg(lbm, torch)
+        log(f"slab64 leg: {out['slab64']}")
     if "batched" in legs:
         out["batched"] = batched_leg(lbm, torch, args.batch_steps, args.graph_steps)
     if not args.no_cpu_baseline:
@@ -260,6 +263,34 @@ def traffic_for(workload, precision, tile):
         key += f"x{tile[3]}steps"
     e = table.get("entries", {}).get(key)
     return None if e is None else e.get("bytes_per_launch")
+
+
+def slab64_leg(lbm, torch, steps=10000):
+    """The 64 x 32 flat interface (C-S 0.8 Tc, tau = 1, improved sigma = 0.1), 10,000
+    steps: a launch-bound lattice of 0.3 MB per step, timed as eager launches and as
+    replays of captured graphs of 100 steps, with the tuned tile."""
+    import synth
+    Tc, _ = lbm.lbm_critical_point(lbm.LBM_EOS_CS, 1.0, 4.0, 1.0, 0.0)
+    rl, rg, _ = lbm.lbm_maxwell(lbm.LBM_EOS_CS, 1.0, 4.0, 1.0, 0.0, 0.8 * Tc)
+    rho0 = synth.slab(64, 32, rl, rg, 16, 48, 2.0, 0.01, synth.BASE_SEED)
+    p = lbm.params(64, 32, tau=1.0, T=0.8 * Tc, scheme=lbm.LBM_SCHEME_IMPROVED, sigma=0.1,
+                   eos=lbm.LBM_EOS_CS, a=1.0, b=4.0, R=1.0, omega=0.0)
+    res = {}
+    for name, k in (("eager", 0), ("graph100", 100)):
+        lat = lbm.Lattice(p, rho0, device="cuda:0")
+        lat.tune()
+        if k:
+            lat.set_graph_steps(k)
+        lat.step(200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[f"{name}_us_per_step"] = round(wall / steps * 1e6, 3)
+        res[f"{name}_tile"] = list(lat.get_tile())
+        lat.close()
+    return res
 
 
 def batched_leg(lbm, torch, batch_steps, graph_steps):

@@ -808,8 +808,9 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, in
   for (int nw : kStepWaves) {
     if (nw > 1 && 64 * (nw / 2) >= c->p.nx) continue;
     for (int pf : {1, 2})
-      for (int L : {0, 4, 8, 16, 32, 64, 128})
-        if (L <= 2 * c->p.ny) cand.push_back(Tile{nw, L, pf, 1});
+      for (int L : {0, 1, 2, 4, 8, 16, 32, 64, 128})
+        if (L <= 2 * c->p.ny && (L == 0 || L > 2 || nodes < (1 << 20)))  // 1-2 rows: small lattices
+          cand.push_back(Tile{nw, L, pf, 1});
   }
   for (int nw : kStep2Waves) {
     if (nw > 4 && 64 * (nw / 2) >= c->p.nx) continue;

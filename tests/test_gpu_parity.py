@@ -104,7 +104,7 @@ def test_tile_shapes_bitwise_identical(L):
     rho0 = slab_rho(200, 90, CS, 0.8, seed=3)
     outs = []
     for tile in [(1, 4, 1), (1, 16, 2), (2, 8, 1), (4, 128, 2), (4, 5, 2), (2, 33, 1), (1, 0, 2),
-                 (4, 0, 1), (2, 0, 2), (8, 0, 2), (16, 7, 1),
+                 (4, 0, 1), (2, 0, 2), (8, 0, 2), (16, 7, 1), (1, 1, 2), (2, 2, 1),
                  # two steps per launch (37 steps: 18 launches and one single step)
                  (4, 0, 2, 2), (4, 5, 1, 2), (8, 16, 2, 2), (8, 128, 1, 2), (4, 33, 2, 2)]:
         lat = L.Lattice(gp, rho0)
