@@ -18,9 +18,15 @@
 // neighbour strips' halo reads hit L2), so a step moves 2*9*sizeof(storage)
 // bytes per node.  The paper gives no kernel design; this layout is ours.
 //
+// k_step2 advances two time steps per launch with the intermediate
+// populations kept on chip (registers and LDS), so the populations cross HBM
+// once per two steps; k_batch_step runs many lattices from one work list.
+// All kernels share the node arithmetic below and give identical bits.
+//
 // Storage: FP64 populations, or deviations s_a = f_a - w_a rho_ref in FP32 /
-// FP16 with FP32 collision arithmetic.  The EOS, psi and force stencil are
-// always evaluated in FP64.
+// FP16 with FP32 collision arithmetic, or FP32 deviations with FP64
+// collision arithmetic.  The EOS, psi and force stencil are always evaluated
+// in FP64.
 #pragma once
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -29,7 +35,7 @@
 
 namespace lbm {
 
-constexpr int LMAX = 128;  // largest chunk height (rows) a work-group marches
+constexpr int LMAX = 128;  // largest chunk height (rows) k_step marches (halo arrays in LDS)
 
 // Per-lattice constants, prepared on the host.
 struct RunDev {
@@ -87,8 +93,9 @@ template <> struct Store<__half> {
   static __device__ __forceinline__ R round(R v) { return __half2float(__float2half_rn(v)); }
 };
 
-__device__ constexpr int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ constexpr int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+// D2Q9 directions e0=(0,0), e1=(1,0), e2=(0,1), e3=(-1,0), e4=(0,-1), e5=(1,1),
+// e6=(-1,1), e7=(-1,-1), e8=(1,-1) (pull9, collide and the moments use this
+// numbering); weights of Eq. (2):
 __device__ constexpr double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                                      1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
