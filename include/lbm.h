@@ -220,10 +220,13 @@ int lbm_batch_coexistence(lbm_batch* b, double* rho_l, double* rho_g, int32_t* s
 int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double* vy, double* p);
 int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f);
 /* Tiles of the batch work list (rows = 0: one item per strip of up to 128
- * rows), tuned over the whole batch like lbm_tune; waves in {1, 2, 4, 8}. */
-int lbm_batch_tune(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth);
-int lbm_batch_set_tile(lbm_batch* b, int32_t waves, int32_t rows, int32_t depth);
-int lbm_batch_get_tile(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth);
+ * rows; rows otherwise >= 4), tuned over the whole batch like lbm_tune;
+ * waves in {1, 2, 4, 8}; steps = 2 (waves 4 or 8) runs two time steps per
+ * launch as for a single lattice, with strips of at most 64*waves - 6
+ * columns. */
+int lbm_batch_tune(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
+int lbm_batch_set_tile(lbm_batch* b, int32_t waves, int32_t rows, int32_t depth, int32_t steps);
+int lbm_batch_get_tile(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
 int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k);
 /* Lattice updates per step summed over runs that are still active. */
 int lbm_batch_nodes(lbm_batch* b, int64_t* nodes);

@@ -621,6 +621,34 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step(const typename Store<S>:
   }
 }
 
+// Persistent batched launch of two steps (tile_step2) over a work list whose
+// items are at most 64*NW - 6 columns wide.  A run frozen by divergence at an
+// earlier launch is skipped; grid must be a multiple of 8.
+template <typename S, int NW, int PF>
+__global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>::E* __restrict__ src,
+                                                         typename Store<S>::E* __restrict__ dst,
+                                                         const RunDev* __restrict__ runs,
+                                                         const Item* __restrict__ items, int nitems,
+                                                         const unsigned long long* stepbase,
+                                                         unsigned long long steplocal,
+                                                         unsigned long long* flags) {
+  using R = typename Store<S>::R;
+  __shared__ double ring1[4][64 * NW];
+  __shared__ double ring2[4][64 * NW];
+  __shared__ R xch[6][64 * NW];
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, nb = gridDim.x >> 3;
+  const int lo = (int)((int64_t)nitems * xcd / 8), hi = (int)((int64_t)nitems * (xcd + 1) / 8);
+  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
+  for (int i = lo + slot; i < hi; i += nb) {
+    const Item it = items[i];
+    const RunDev d = runs[it.run];
+    if (flags[it.run] < step) continue;
+    tile_step2<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
+                          &flags[it.run], ring1, ring2, xch);
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
 // Graph helper: advance the device step counter after k steps.
 __global__ void k_counter_add(unsigned long long* ctr, unsigned long long k) { *ctr += k; }
 __global__ void k_counter_set(unsigned long long* ctr, unsigned long long v) { *ctr = v; }

@@ -335,9 +335,45 @@ hipError_t launch_batch_s(const Tile& t, const void* src, void* dst, const RunDe
   }
 }
 
+template <typename S, int NW, int PF>
+hipError_t launch_batch2_t(const void* src, void* dst, const RunDev* runs, const Item* items,
+                           int nitems, const unsigned long long* base, unsigned long long local,
+                           unsigned long long* flags, hipStream_t st) {
+  int g = resident_blocks((const void*)k_batch_step2<S, NW, PF>, 64 * NW);
+  g = std::min(g, (nitems + 7) / 8 * 8);
+  g = std::max(8, g / 8 * 8);
+  using E = typename Store<S>::E;
+  hipLaunchKernelGGL((k_batch_step2<S, NW, PF>), dim3(g), dim3(64 * NW), 0, st,
+                     static_cast<const E*>(src), static_cast<E*>(dst), runs, items, nitems, base,
+                     local, flags);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_batch2_s(const Tile& t, const void* src, void* dst, const RunDev* runs,
+                           const Item* items, int nitems, const unsigned long long* base,
+                           unsigned long long local, unsigned long long* flags, hipStream_t st) {
+  switch (t.nw * 10 + t.pf) {
+    case 41: return launch_batch2_t<S, 4, 1>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 42: return launch_batch2_t<S, 4, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 81: return launch_batch2_t<S, 8, 1>(src, dst, runs, items, nitems, base, local, flags, st);
+    default: return launch_batch2_t<S, 8, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+  }
+}
+
+// One launch of the batch tile: t.ts time steps (1 or 2) of every active run.
 hipError_t launch_batch(int prec, const Tile& t, const void* src, void* dst, const RunDev* runs,
                         const Item* items, int nitems, const unsigned long long* base,
                         unsigned long long local, unsigned long long* flags, hipStream_t st) {
+  if (t.ts == 2) {
+    if (prec == LBM_PREC_F64)
+      return launch_batch2_s<double>(t, src, dst, runs, items, nitems, base, local, flags, st);
+    if (prec == LBM_PREC_F32DEV)
+      return launch_batch2_s<float>(t, src, dst, runs, items, nitems, base, local, flags, st);
+    if (prec == LBM_PREC_F32DEV_F64)
+      return launch_batch2_s<f32s_f64a>(t, src, dst, runs, items, nitems, base, local, flags, st);
+    return launch_batch2_s<__half>(t, src, dst, runs, items, nitems, base, local, flags, st);
+  }
   if (prec == LBM_PREC_F64)
     return launch_batch_s<double>(t, src, dst, runs, items, nitems, base, local, flags, st);
   if (prec == LBM_PREC_F32DEV)
@@ -935,14 +971,23 @@ BatchLayout batch_layout(int n, const lbm_params* p) {
 }
 
 // Work list: tiles of every run; L = 0 means one item per whole strip column.
+// Work list of a tile: per run, chunks of L rows (at most LMAX) times strips of
+// 64*nw columns, or for the two-step tile strips of at most 64*nw - 6 columns
+// spread evenly over the run's width (such items also suit the one-step
+// kernel, which runs an odd remainder step).
 int batch_items(lbm_batch* b, const Tile& t) {
   std::vector<Item> items;
   const int SW = 64 * t.nw;
   for (int r = 0; r < b->nruns; ++r) {
-    const int L = t.L > 0 ? t.L : std::min(b->p[r].ny, LMAX);
-    for (int y0 = 0; y0 < b->p[r].ny; y0 += L)
-      for (int x0 = 0; x0 < b->p[r].nx; x0 += SW)
-        items.push_back(Item{r, x0, y0, std::min(SW, b->p[r].nx - x0), std::min(L, b->p[r].ny - y0), 0});
+    const int nx = b->p[r].nx, ny = b->p[r].ny;
+    const int L = t.L > 0 ? t.L : std::min(ny, LMAX);
+    const int ns = t.ts == 2 ? (nx + SW - 7) / (SW - 6) : (nx + SW - 1) / SW;
+    for (int y0 = 0; y0 < ny; y0 += L)
+      for (int sx = 0; sx < ns; ++sx) {
+        const int x0 = t.ts == 2 ? (int)((int64_t)sx * nx / ns) : sx * SW;
+        const int x1 = t.ts == 2 ? (int)((int64_t)(sx + 1) * nx / ns) : std::min(nx, x0 + SW);
+        items.push_back(Item{r, x0, y0, x1 - x0, std::min(L, ny - y0), 0});
+      }
   }
   if ((int)items.size() > b->items_cap) return LBM_ENOSPACE;
   HIPCHK(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, b->st));
@@ -964,10 +1009,11 @@ int batch_capture(lbm_batch* b, int parity) {
   hipGraph_t g;
   HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int i = 0; i < b->graph_k && e == hipSuccess; ++i) {
+  const int launches = b->graph_k / b->tile.ts;  // graph_k is even
+  for (int i = 0; i < launches && e == hipSuccess; ++i) {
     const int s = (parity + i) & 1;
     e = launch_batch(b->prec, b->tile, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
-                     b->ctr, (unsigned long long)i, b->flags, b->st);
+                     b->ctr, (unsigned long long)i * b->tile.ts, b->flags, b->st);
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_counter_add, dim3(1), dim3(1), 0, b->st, b->ctr, (unsigned long long)b->graph_k);
@@ -1116,26 +1162,31 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
       HIPCHK(hipGraphLaunch(b->gexec[b->cur], b->st));
       done += b->graph_k;
       b->step += b->graph_k;
+      b->cur ^= (b->graph_k / b->tile.ts) & 1;  // one buffer swap per launch
     }
   }
-  for (; done < n; ++done) {
+  while (done < n) {
     const int s = b->cur;
-    HIPCHK(launch_batch(b->prec, b->tile, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+    Tile t = b->tile;
+    if (n - done < t.ts) t.ts = 1;  // odd remainder of a two-step tile (its items suit both)
+    HIPCHK(launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
                         nullptr, (unsigned long long)b->step, b->flags, b->st));
     b->cur ^= 1;
-    b->step += 1;
+    b->step += t.ts;
+    done += t.ts;
   }
   return LBM_OK;
 }
 
-int lbm_batch_set_tile(lbm_batch* b, int32_t nw, int32_t L, int32_t depth) {
-  if (!b || !valid_tile(nw, L, depth, 8) || (L > 0 && L < 4)) return LBM_EINVAL;
+int lbm_batch_set_tile(lbm_batch* b, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
+  if (!b || !valid_tile(nw, L, depth, 8, steps) || (L > 0 && L < 4)) return LBM_EINVAL;
   batch_drop_graphs(b);
-  return batch_items(b, Tile{nw, L, depth});
+  return batch_items(b, Tile{nw, L, depth, steps});
 }
 
-int lbm_batch_get_tile(lbm_batch* b, int32_t* nw, int32_t* L, int32_t* depth) {
+int lbm_batch_get_tile(lbm_batch* b, int32_t* nw, int32_t* L, int32_t* depth, int32_t* steps) {
   if (!b) return LBM_EINVAL;
+  if (steps) *steps = b->tile.ts;
   if (nw) *nw = b->tile.nw;
   if (L) *L = b->tile.L;
   if (depth) *depth = b->tile.pf;
@@ -1150,34 +1201,41 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k) {
   return LBM_OK;
 }
 
-int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth_out) {
+int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth_out,
+                   int32_t* steps_out) {
   if (!b) return LBM_EINVAL;
   float best = 1e30f;
   Tile bt = b->tile;
   const int s = b->cur;
   int maxnx = 0;
   for (int r = 0; r < b->nruns; ++r) maxnx = std::max(maxnx, b->p[r].nx);
+  std::vector<Tile> cand;
   for (int nw : kBatchWaves) {
     if (nw > 1 && 64 * (nw / 2) >= maxnx) continue;
     for (int pf : {1, 2})
-      for (int L : {0, 4, 8, 16, 32, 64}) {
-        const Tile t{nw, L, pf};
-        int st = batch_items(b, t);
-        if (st == LBM_ENOSPACE) continue;
-        if (st != LBM_OK) return st;
-        const float ms = time_launches(
-            b->st,
-            [&] {
-              return launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items,
-                                  b->nitems, nullptr, (unsigned long long)b->step, b->flags, b->st);
-            },
-            5);
-        if (ms < 0) return LBM_EHIP;
-        if (ms < best) {
-          best = ms;
-          bt = t;
-        }
-      }
+      for (int L : {0, 4, 8, 16, 32, 64}) cand.push_back(Tile{nw, L, pf, 1});
+  }
+  for (int nw : kStep2Waves) {
+    if (nw > 4 && 64 * (nw / 2) >= maxnx) continue;
+    for (int pf : {1, 2})
+      for (int L : {0, 32, 64}) cand.push_back(Tile{nw, L, pf, 2});
+  }
+  for (const Tile& t : cand) {
+    int st = batch_items(b, t);
+    if (st == LBM_ENOSPACE) continue;
+    if (st != LBM_OK) return st;
+    const float ms = time_launches(
+        b->st,
+        [&] {
+          return launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items,
+                              b->nitems, nullptr, (unsigned long long)b->step, b->flags, b->st);
+        },
+        5);
+    if (ms < 0) return LBM_EHIP;
+    if (ms / t.ts < best) {  // time per lattice step
+      best = ms / t.ts;
+      bt = t;
+    }
   }
   batch_drop_graphs(b);
   int st = batch_items(b, bt);
@@ -1189,6 +1247,7 @@ int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth
   if (nw_out) *nw_out = bt.nw;
   if (L_out) *L_out = bt.L;
   if (depth_out) *depth_out = bt.pf;
+  if (steps_out) *steps_out = bt.ts;
   return LBM_OK;
 }
 

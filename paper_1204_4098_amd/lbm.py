@@ -74,9 +74,9 @@ _SIGS = {
     "lbm_batch_coexistence": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_batch_moments": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "lbm_batch_get_populations": (C.c_int, [_vp, C.c_int32, _vp]),
-    "lbm_batch_tune": (C.c_int, [_vp, _ip, _ip, _ip]),
-    "lbm_batch_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
-    "lbm_batch_get_tile": (C.c_int, [_vp, _ip, _ip, _ip]),
+    "lbm_batch_tune": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
+    "lbm_batch_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "lbm_batch_get_tile": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     "lbm_batch_set_graph_steps": (C.c_int, [_vp, C.c_int32]),
     "lbm_batch_nodes": (C.c_int, [_vp, _lp]),
     "lbm_batch_destroy": (C.c_int, [_vp]),
@@ -328,17 +328,20 @@ class Batch:
         return f
 
     def tune(self):
-        w, r, d = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(lib().lbm_batch_tune(self.b, C.byref(w), C.byref(r), C.byref(d)), "lbm_batch_tune")
-        return w.value, r.value, d.value
+        """Fastest tile per lattice step: (waves, rows, depth, steps per launch)."""
+        w, r, d, k = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbm_batch_tune(self.b, C.byref(w), C.byref(r), C.byref(d), C.byref(k)), "lbm_batch_tune")
+        return w.value, r.value, d.value, k.value
 
-    def set_tile(self, waves: int, rows: int, depth: int = 2):
-        _check(lib().lbm_batch_set_tile(self.b, int(waves), int(rows), int(depth)), "lbm_batch_set_tile")
+    def set_tile(self, waves: int, rows: int, depth: int = 2, steps: int = 1):
+        _check(lib().lbm_batch_set_tile(self.b, int(waves), int(rows), int(depth), int(steps)),
+               "lbm_batch_set_tile")
 
     def get_tile(self):
-        w, r, d = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(lib().lbm_batch_get_tile(self.b, C.byref(w), C.byref(r), C.byref(d)), "lbm_batch_get_tile")
-        return w.value, r.value, d.value
+        w, r, d, k = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lbm_batch_get_tile(self.b, C.byref(w), C.byref(r), C.byref(d), C.byref(k)),
+               "lbm_batch_get_tile")
+        return w.value, r.value, d.value, k.value
 
     def set_graph_steps(self, k: int):
         _check(lib().lbm_batch_set_graph_steps(self.b, int(k)), "lbm_batch_set_graph_steps")

@@ -111,7 +111,7 @@ def _batch_runs(L, prec=0):
     return gps, ops, rhos
 
 
-@pytest.mark.parametrize("tile", [(1, 16, 2), (2, 0, 1), (4, 8, 2), (8, 0, 2)])
+@pytest.mark.parametrize("tile", [(1, 16, 2), (2, 0, 1), (4, 8, 2), (8, 0, 2), (4, 0, 2, 2), (8, 32, 1, 2)])
 def test_batch_equals_single_runs_bitwise(L, tile):
     gps, _, rhos = _batch_runs(L)
     b = L.Batch(gps, rhos)
@@ -167,12 +167,17 @@ def test_batch_divergence_is_isolated(L):
     b.close()
 
 
-def test_batch_graph_bitwise(L):
+@pytest.mark.parametrize("tile,k", [((2, 8, 1), 12), ((4, 0, 2, 2), 12), ((4, 32, 1, 2), 10)])
+def test_batch_graph_bitwise(L, tile, k):
+    # graph replays (for two steps per launch: k/2 launches, odd for k = 10) against eager
+    # single steps, FP32 deviations
     gps, _, rhos = _batch_runs(L, prec=1)
     a = L.Batch(gps, rhos)
+    a.set_tile(1, 16, 2)
     a.step(90)
     b = L.Batch(gps, rhos)
-    b.set_graph_steps(12)
+    b.set_tile(*tile)
+    b.set_graph_steps(k)
     b.step(5)
     b.step(85)
     for i in range(len(gps)):
