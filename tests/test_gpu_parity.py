@@ -157,6 +157,23 @@ def test_two_step_graph_replay_bitwise(L, k):
     a.close(); b.close()
 
 
+@pytest.mark.parametrize("scheme,eos,t", [(0, CS, 0.85), (1, CS, 0.85), (3, CS, 0.85), (4, CS, 0.95),
+                                          (0, PR, 0.8), (2, PR, 0.8)])
+def test_two_step_schemes_bitwise(L, scheme, eos, t):
+    # every forcing scheme and both equations of state through two-step launches
+    gp, _ = pair(L, 300, 70, t=t, tau=0.7, scheme=scheme, sigma=0.105, eos=eos)
+    rho0 = slab_rho(300, 70, eos, t, seed=8)
+    outs = []
+    for tile in [(2, 8, 1), (4, 0, 2, 2), (8, 16, 1, 2)]:
+        lat = L.Lattice(gp, rho0)
+        lat.set_tile(*tile)
+        lat.step(41)
+        outs.append(lat.get_populations()[0])
+        assert lat.status()[0] == L.LBM_OK
+        lat.close()
+    assert np.array_equal(outs[1], outs[0]) and np.array_equal(outs[2], outs[0])
+
+
 @pytest.mark.parametrize("shape", [(3, 3), (5, 4), (130, 7), (260, 5)])
 def test_two_step_edge_shapes(L, shape):
     nx, ny = shape
