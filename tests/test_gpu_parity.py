@@ -158,7 +158,7 @@ def test_two_step_graph_replay_bitwise(L, k):
 
 
 @pytest.mark.parametrize("scheme,eos,t", [(0, CS, 0.85), (1, CS, 0.85), (3, CS, 0.85), (4, CS, 0.95),
-                                          (0, PR, 0.8), (2, PR, 0.8)])
+                                          (1, PR, 0.8), (2, PR, 0.8)])
 def test_two_step_schemes_bitwise(L, scheme, eos, t):
     # every forcing scheme and both equations of state through two-step launches
     gp, _ = pair(L, 300, 70, t=t, tau=0.7, scheme=scheme, sigma=0.105, eos=eos)
