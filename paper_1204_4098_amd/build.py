@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "liblbm_hip.so")
 SOURCES = ["lbm_lib.hip", "thermo.cpp", "mlp.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-ffp-contract=fast", "-munsafe-fp-atomics"]
+         "-ffp-contract=fast-honor-pragmas", "-munsafe-fp-atomics"]
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace lbm {
 
@@ -418,6 +419,15 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
 // behind step one; one row of the march takes two barriers.  Both steps use
 // the same arithmetic, in the same order, as two single-step launches, so the
 // result is bitwise identical.
+// Row modes of tile_step2 (bit set): a steady row, and the phases that run
+// on every lane of the block instead of on their own lane range.
+constexpr int kRowPsi = 1, kRowPull2 = 2, kRowCollide1 = 4, kRowCollide2 = 8, kRowSteady = 16;
+// Mode of the steady rows per storage type, chosen by measurement on the
+// 4096 x 4096 droplet workload.
+template <typename S> struct SteadyMode
+    : std::integral_constant<int, kRowSteady | kRowPsi | kRowPull2 | kRowCollide1 | kRowCollide2> {};
+template <> struct SteadyMode<double> : std::integral_constant<int, kRowSteady | kRowPull2> {};
+
 template <typename S, int NW, int PF>
 __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restrict__ src,
                                            typename Store<S>::E* __restrict__ dst,
@@ -434,15 +444,18 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   const bool act1 = tid >= 1 && tid < n0 - 1;       // lanes that run step one
   const bool pull2 = tid >= 2 && tid < n0 - 2;      // lanes that pull for step two
   const bool out = tid >= 3 && tid < ncols + 3;     // lanes that write step two
+  // LDS neighbour index: tid on every lane of the ranges above, kept inside
+  // the rows for lanes 0 and 64*NW-1
+  const int tc = min(max(tid, 1), 64 * NW - 2);
   auto wrapx = [&](int x) { return x < 0 ? x + d.nx : (x >= d.nx ? x - d.nx : x); };
   auto wrapy = [&](int y) { return y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y); };
-  const Cols cx = cols_of(wrapx(x0 - 3 + (act0 ? tid : 0)), d.nx);
+  const Cols cx = cols_of(wrapx(x0 - 3 + min(tid, n0 - 1)), d.nx);
   const double rref = d.rho_ref;
   bool bad1 = false, bad2 = false;
   const int ya = y0 - 3;                            // first psi(t) row
 
   // preload: psi(t) of rows y0-3 (ring slot 0) and y0-2 (slot 1); pulled row y0-2
-  R fc[9], fn[9];
+  R fc[9] = {}, fn[9] = {};
   double psi2c = 0.0;
   if (act0) {
     R f[9];
@@ -456,25 +469,33 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
 
   // f*(t+1) of the last three step-one rows, kept for step two:
   // gA = row y1-1 (all 9), gB = row y1-2 (0,1,3,2,5,6), gC = row y1-3 (2,5,6)
-  R gA[9], gB[6], gC[3];
-  R hp[9];          // step-two pulled populations of the row collided next
+  R gA[9] = {}, gB[6] = {}, gC[3] = {};
+  R hp[9] = {};     // step-two pulled populations of the row collided next
   double psi2p = 0.0;
   const int n_one = nrows + 4;                      // step-one rows y0-2 .. y0+nrows+1
-  for (int j = 0; j < n_one + 1; ++j) {
+  // One row of the march.  Mode (SteadyMode) bit 16 marks a steady row, in
+  // which every row condition below holds; bits 1, 2, 4, 8 make a phase run
+  // on every lane of the block: lanes outside the phase's range compute values
+  // that no lane in range reads (their LDS slots are read only by lanes
+  // outside the ranges too, and tc keeps their neighbour reads inside the
+  // rows), so that phase carries no per-lane branch apart from the store.
+  auto row = [&](const int j, auto mode) __attribute__((always_inline)) {
+    constexpr int M = decltype(mode)::value;
+    constexpr bool St = (M & kRowSteady) != 0;
     const int y1 = y0 - 2 + j;                      // step-one row collided at this j
     // ---- phase 1: psi(t) of row y1+1; exchange of the rows step two pulls
     R fnn[9];
     double psi2n = 0.0;
-    if (j < n_one && act0) {
+    if ((St || j < n_one) && ((M & kRowPsi) || act0)) {
       if (PF == 2) {
-        if (j + 1 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 2), fnn);
+        if (St || j + 1 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 2), fnn);
       } else {
         pull9<S>(src, d, cx, wrapy(y1 + 1), fn);
       }
       psi2n = psi2_of(rref + double(sum9(fn)), d);
       ring1[(j + 2) & 3][tid] = sqrt(psi2n);
     }
-    if (j >= 3 && act1) {  // step two pulls row q = y1 - 2 below
+    if ((St || j >= 3) && ((M & kRowPsi) || act1)) {  // step two pulls row q = y1 - 2 below
       xch[0][tid] = gB[1];
       xch[1][tid] = gB[2];
       xch[2][tid] = gC[1];
@@ -487,31 +508,32 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
     const int q = y1 - 2;
     R hn[9];
     double psi2q = 0.0;
-    if (j >= 3 && pull2) {
+    if ((St || j >= 3) && ((M & kRowPull2) || pull2)) {
       hn[0] = gB[0];
-      hn[1] = xch[0][tid - 1];
+      hn[1] = xch[0][tc - 1];
       hn[2] = gC[0];
-      hn[3] = xch[1][tid + 1];
+      hn[3] = xch[1][tc + 1];
       hn[4] = gA[4];
-      hn[5] = xch[2][tid - 1];
-      hn[6] = xch[3][tid + 1];
-      hn[7] = xch[4][tid + 1];
-      hn[8] = xch[5][tid - 1];
+      hn[5] = xch[2][tc - 1];
+      hn[6] = xch[3][tc + 1];
+      hn[7] = xch[4][tc + 1];
+      hn[8] = xch[5][tc - 1];
       psi2q = psi2_of(rref + double(sum9(hn)), d);
       ring2[(q - (y0 - 1)) & 3][tid] = sqrt(psi2q);
     }
-    if (j >= 1) {  // rotate the kept step-one rows (gA was produced at j-1)
+    if (St || j >= 1) {  // rotate the kept step-one rows (gA was produced at j-1)
       gC[0] = gB[3]; gC[1] = gB[4]; gC[2] = gB[5];
       gB[0] = gA[0]; gB[1] = gA[1]; gB[2] = gA[3];
       gB[3] = gA[2]; gB[4] = gA[5]; gB[5] = gA[6];
     }
-    if (j < n_one && act0) {
-      if (act1) {
+    if ((St || j < n_one) && ((M & kRowCollide1) || act0)) {
+      if ((M & kRowCollide1) || act1) {
         double Fx, Fy;
-        force3x3(ring1[j & 3], ring1[(j + 1) & 3], ring1[(j + 2) & 3], tid, d.mG, Fx, Fy);
+        force3x3(ring1[j & 3], ring1[(j + 1) & 3], ring1[(j + 2) & 3], tc, d.mG, Fx, Fy);
         const R drho = sum9(fc);
         const double rho64 = rref + double(drho);
-        if (out && y1 >= y0 && y1 < y0 + nrows) bad1 |= !(psi2c > 0.0) || !(rho64 > 0.0);
+        const bool chk = out && y1 >= y0 && y1 < y0 + nrows;
+        bad1 |= chk && (!(psi2c > 0.0) || !(rho64 > 0.0));
         const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
         collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
 #pragma unroll
@@ -520,7 +542,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
 #pragma unroll
       for (int a = 0; a < 9; ++a) fc[a] = fn[a];
       psi2c = psi2n;
-      if (PF == 2 && j + 1 < n_one) {
+      if (PF == 2 && (St || j + 1 < n_one)) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) fn[a] = fnn[a];
       }
@@ -528,25 +550,33 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
     __syncthreads();
     // ---- phase 3: step-two collide of row r = q-1 and store
     const int r = q - 1;
-    if (j >= 4 && out && r >= y0 && r < y0 + nrows) {
+    if ((St || (j >= 4 && r >= y0 && r < y0 + nrows)) && ((M & kRowCollide2) || out)) {
       double Fx, Fy;
       force3x3(ring2[(r - 1 - (y0 - 1)) & 3], ring2[(r - (y0 - 1)) & 3], ring2[(q - (y0 - 1)) & 3],
-               tid, d.mG, Fx, Fy);
+               tc, d.mG, Fx, Fy);
       const R drho = sum9(hp);
       const double rho64 = rref + double(drho);
-      bad2 |= !(psi2p > 0.0) || !(rho64 > 0.0);
+      bad2 |= out && (!(psi2p > 0.0) || !(rho64 > 0.0));
       const R ip2 = d.sig != 0.0 ? rcp(R(psi2p)) : R(0);
       collide<R>(hp, drho, R(rho64), mom_x(hp), mom_y(hp), R(Fx), R(Fy), ip2, d);
-      typename T::E* row = dst + (int64_t)wrapy(r) * d.pitch;
+      if (out) {
+        typename T::E* orow = dst + (int64_t)wrapy(r) * d.pitch;
 #pragma unroll
-      for (int a = 0; a < 9; ++a) T::st(row + a * d.plane + cx.x, hp[a]);
+        for (int a = 0; a < 9; ++a) T::st(orow + a * d.plane + cx.x, hp[a]);
+      }
     }
-    if (j >= 3) {
+    if (St || j >= 3) {
 #pragma unroll
       for (int a = 0; a < 9; ++a) hp[a] = hn[a];
       psi2p = psi2q;
     }
-  }
+  };
+  // rows 0..4 fill the pipeline, 5 .. n_one-2 are steady, the last two drain it
+  using Edge = std::integral_constant<int, 0>;
+  using Steady = std::integral_constant<int, SteadyMode<S>::value>;
+  for (int j = 0; j < 5; ++j) row(j, Edge{});
+  for (int j = 5; j < n_one - 1; ++j) row(j, Steady{});
+  for (int j = max(5, n_one - 1); j < n_one + 1; ++j) row(j, Edge{});
   // divergence: the first step that saw a bad node (one atomic per wave)
   const auto b1 = __ballot(bad1), b2 = __ballot(bad2);
   if (__lane_id() == 0 && (b1 | b2) != 0) atomicMin(flag, b1 != 0 ? step : step + 1);
