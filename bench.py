@@ -97,6 +97,48 @@ def cpu_baseline(kw, rho0, sample_n=256, steps=None, budget_s=15.0):
                       f"FP64 C oracle, one thread, {el:.1f} s"}
 
 
+def cpu_pool_baseline(sample_runs=16, lups_per_run=3e7):
+    """Multi-core oracle throughput on the batched workload: every (256 / sample_runs)-th
+    of the 256 flat-interface runs (evenly spaced, so the size mix is kept),
+    each advanced by the FP64 C oracle for about lups_per_run lattice updates,
+    one run per task on a thread pool over the host cores (the oracle's C step
+    releases the GIL).  Initial states are the runs' own slabs between the
+    oracle's Maxwell densities."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import synth
+    from oracle import lbm as olbm
+    from oracle import thermo as th
+    runs = synth.sweep_runs(256)
+    pick = list(range(0, 256, 256 // sample_runs))[:sample_runs]
+    Tc = th.critical_cs()[0]
+    tasks = []
+    for i in pick:
+        r = runs[i]
+        c = th.maxwell_cs(r["t_over_tc"])
+        op = olbm.Params(nx=r["nx"], ny=r["ny"], tau=r["tau"], G=-1.0, eos=0, a=1.0, b=4.0, R=1.0,
+                         T=r["t_over_tc"] * Tc, omega=0.0, Tc=Tc, scheme=olbm.SCHEME_IMPROVED,
+                         sigma=r["sigma"])
+        rho0 = synth.slab(r["nx"], r["ny"], float(c.rho_l), float(c.rho_g), r["nx"] / 4,
+                          3 * r["nx"] / 4, 2.0, 0.01, synth.BASE_SEED, i)
+        steps = max(1, round(lups_per_run / (r["nx"] * r["ny"])))
+        tasks.append((op, olbm.init_equilibrium(rho0), steps))
+    cores = min(16, len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        res = list(ex.map(lambda t: olbm.step(t[0], t[1], t[2]), tasks))
+    el = time.perf_counter() - t0
+    # a diverged run stops at its divergence step: count the updates done
+    done = [t[2] if st == olbm.OK else max(0, dv) for t, (st, dv) in zip(tasks, res)]
+    lups = sum(t[0].nx * t[0].ny * n for t, n in zip(tasks, done))
+    ndiv = sum(st != olbm.OK for st, _ in res)
+    return {"value": round(lups / el / 1e6, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{len(tasks)} of the 256 batched flat-interface runs (every "
+                      f"{256 // sample_runs}th; {ndiv} diverged and stopped early), "
+                      f"~{lups_per_run:.0e} lattice updates each, FP64 C oracle, one run per "
+                      f"thread, {lups:.2e} updates in {el:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +245,10 @@ def main():
         out["batched"] = batched_leg(lbm, torch, args.batch_steps, args.graph_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(kw, rho0)
+        if "batched" in legs:
+            out["cpu_baseline"]["batched_pool"] = cpu_pool_baseline()
+            log(f"cpu pool oracle on batched runs: {out['cpu_baseline']['batched_pool']['value']} "
+                f"MLUPS on {out['cpu_baseline']['batched_pool']['cores']} cores")
     print(json.dumps(out), flush=True)
 
 
