@@ -427,6 +427,12 @@ constexpr int kRowPsi = 1, kRowPull2 = 2, kRowCollide1 = 4, kRowCollide2 = 8, kR
 template <typename S> struct SteadyMode
     : std::integral_constant<int, kRowSteady | kRowPsi | kRowPull2 | kRowCollide1 | kRowCollide2> {};
 template <> struct SteadyMode<double> : std::integral_constant<int, kRowSteady | kRowPull2> {};
+// Steady rows per loop iteration (1 to 3), measured likewise.  Unrolling by 3
+// removes the rotation moves but adds registers; it pays only for FP32
+// storage with FP64 arithmetic (FP64 storage: 7 % fewer VALU instructions per
+// row yet 5 % slower; FP32 and FP16: 3 waves per SIMD would drop to 2).
+template <typename S> struct SteadyUnroll : std::integral_constant<int, 1> {};
+template <> struct SteadyUnroll<f32s_f64a> : std::integral_constant<int, 3> {};
 
 template <typename S, int NW, int PF>
 __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restrict__ src,
@@ -575,7 +581,19 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   using Edge = std::integral_constant<int, 0>;
   using Steady = std::integral_constant<int, SteadyMode<S>::value>;
   for (int j = 0; j < 5; ++j) row(j, Edge{});
-  for (int j = 5; j < n_one - 1; ++j) row(j, Steady{});
+  // Steady rows U at a time (a loop with barriers is not unrolled by the
+  // compiler): with U = 3, the period of the kept-row rotations (gA -> gB ->
+  // gC, fnn -> fn -> fc), those rotations become register renaming instead of
+  // moves.
+  constexpr int U = SteadyUnroll<S>::value;
+  int js = 5;
+  for (; js + U <= n_one - 1; js += U) {
+    row(js, Steady{});
+    if constexpr (U > 1) row(js + 1, Steady{});
+    if constexpr (U > 2) row(js + 2, Steady{});
+  }
+  if constexpr (U > 1)
+    for (; js < n_one - 1; ++js) row(js, Steady{});
   for (int j = max(5, n_one - 1); j < n_one + 1; ++j) row(j, Edge{});
   // divergence: the first step that saw a bad node (one atomic per wave)
   const auto b1 = __ballot(bad1), b2 = __ballot(bad2);
