@@ -600,10 +600,19 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   if (__lane_id() == 0 && (b1 | b2) != 0) atomicMin(flag, b1 != 0 ? step : step + 1);
 }
 
+// Order of the balanced schedule's row space per storage type: strip-major,
+// or band-major (eight horizontal bands of rows, each strip's rows of a band
+// contiguous), which gives the blocks of one XCD one band of all strips.
+// Measured on the 4096 x 4096 droplet workload: band-major is 2 % faster for
+// FP64 storage and 3 % slower for FP32 storage with FP64 arithmetic.
+template <typename S> struct Step2BandMajor : std::false_type {};
+template <> struct Step2BandMajor<double> : std::true_type {};
+
 // Two steps per launch over the single lattice; strips of at most 64*NW - 6
 // columns, spread evenly over nx.  L > 0: one block per (strip, L-row chunk);
 // L == 0: balanced schedule, every block marches one contiguous share of the
-// strip-major row space (no length cap: the tile holds no per-row arrays).
+// row space in the order above (no length cap: the tile holds no per-row
+// arrays); a share is split where it crosses a strip or band boundary.
 template <typename S, int NW, int PF>
 __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* __restrict__ src,
                                                    typename Store<S>::E* __restrict__ dst,
@@ -633,9 +642,25 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
   const int64_t total = (int64_t)nstrips * d.ny;
   int64_t r = total * t / gridDim.x;
   const int64_t e = total * (t + 1) / gridDim.x;
+  auto bstart = [&](int k) { return (int)((int64_t)k * d.ny / 8); };
   while (r < e) {
-    const int s = (int)(r / d.ny), y = (int)(r - (int64_t)s * d.ny);
-    const int n = (int)min(e - r, (int64_t)(d.ny - y));
+    int s, y, n;
+    if constexpr (Step2BandMajor<S>::value) {
+      // band-major order: 8 horizontal bands of rows, then strip, then row
+      int k = (int)(r * 8 / total);
+      while (k > 0 && (int64_t)nstrips * bstart(k) > r) --k;
+      while (k < 7 && (int64_t)nstrips * bstart(k + 1) <= r) ++k;
+      const int b0 = bstart(k), rows = bstart(k + 1) - b0;
+      const int64_t rr = r - (int64_t)nstrips * b0;
+      s = (int)(rr / rows);
+      y = b0 + (int)(rr - (int64_t)s * rows);
+      n = (int)min(e - r, (int64_t)(b0 + rows - y));
+    } else {
+      // strip-major order
+      s = (int)(r / d.ny);
+      y = (int)(r - (int64_t)s * d.ny);
+      n = (int)min(e - r, (int64_t)(d.ny - y));
+    }
     int x0, nc;
     strip(s, x0, nc);
     tile_step2<S, NW, PF>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, xch);
