@@ -402,7 +402,22 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
 }
 
 // ---- two time steps per launch ------------------------------------------------
-//
+
+// Row modes of tile_step2 (bit set): a steady row, and the phases that run
+// on every lane of the block instead of on their own lane range.
+constexpr int kRowPsi = 1, kRowPull2 = 2, kRowCollide1 = 4, kRowCollide2 = 8, kRowSteady = 16;
+// Mode of the steady rows per storage type, chosen by measurement on the
+// 4096 x 4096 droplet workload.
+template <typename S> struct SteadyMode
+    : std::integral_constant<int, kRowSteady | kRowPsi | kRowPull2 | kRowCollide1 | kRowCollide2> {};
+template <> struct SteadyMode<double> : std::integral_constant<int, kRowSteady | kRowPull2> {};
+// Steady rows per loop iteration (1 to 3), measured likewise.  Unrolling by 3
+// removes the rotation moves but adds registers; it pays only for FP32
+// storage with FP64 arithmetic (FP64 storage: 7 % fewer VALU instructions per
+// row yet 5 % slower; FP32 and FP16: 3 waves per SIMD would drop to 2).
+template <typename S> struct SteadyUnroll : std::integral_constant<int, 1> {};
+template <> struct SteadyUnroll<f32s_f64a> : std::integral_constant<int, 3> {};
+
 // The populations cross HBM once per two steps.  Lane i of a block owns
 // column c = x0 - 3 + i for both steps, i < ncols + 6:
 //   * every lane pulls its column and evaluates psi(t);
@@ -419,21 +434,6 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
 // behind step one; one row of the march takes two barriers.  Both steps use
 // the same arithmetic, in the same order, as two single-step launches, so the
 // result is bitwise identical.
-// Row modes of tile_step2 (bit set): a steady row, and the phases that run
-// on every lane of the block instead of on their own lane range.
-constexpr int kRowPsi = 1, kRowPull2 = 2, kRowCollide1 = 4, kRowCollide2 = 8, kRowSteady = 16;
-// Mode of the steady rows per storage type, chosen by measurement on the
-// 4096 x 4096 droplet workload.
-template <typename S> struct SteadyMode
-    : std::integral_constant<int, kRowSteady | kRowPsi | kRowPull2 | kRowCollide1 | kRowCollide2> {};
-template <> struct SteadyMode<double> : std::integral_constant<int, kRowSteady | kRowPull2> {};
-// Steady rows per loop iteration (1 to 3), measured likewise.  Unrolling by 3
-// removes the rotation moves but adds registers; it pays only for FP32
-// storage with FP64 arithmetic (FP64 storage: 7 % fewer VALU instructions per
-// row yet 5 % slower; FP32 and FP16: 3 waves per SIMD would drop to 2).
-template <typename S> struct SteadyUnroll : std::integral_constant<int, 1> {};
-template <> struct SteadyUnroll<f32s_f64a> : std::integral_constant<int, 3> {};
-
 template <typename S, int NW, int PF>
 __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restrict__ src,
                                            typename Store<S>::E* __restrict__ dst,
