@@ -62,7 +62,11 @@ struct Item {
 };
 
 // Storage traits: E = element type in memory, R = collision arithmetic type;
-// round(v) = the value a store followed by a load would give.
+// round(v) = the value a store followed by a load would give.  Cache policy
+// per type, measured on the 4096 x 4096 droplet workload with the two-step
+// kernel: FP64 populations stream with non-temporal loads and stores (plain
+// stores cost 10 %); FP32 deviations use plain loads and stores (9 % faster
+// than non-temporal); FP32 storage with FP64 arithmetic shows no difference.
 struct f32s_f64a {};  // FP32 deviation storage with FP64 collision arithmetic
 template <typename S> struct Store;
 template <> struct Store<double> {
@@ -75,8 +79,8 @@ template <> struct Store<double> {
 template <> struct Store<float> {
   using E = float;
   using R = float;
-  static __device__ __forceinline__ R ld(const E* p) { return __builtin_nontemporal_load(p); }
-  static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ R ld(const E* p) { return *p; }
+  static __device__ __forceinline__ void st(E* p, R v) { *p = v; }
   static __device__ __forceinline__ R round(R v) { return v; }
 };
 template <> struct Store<f32s_f64a> {
