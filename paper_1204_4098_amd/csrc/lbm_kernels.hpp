@@ -66,7 +66,8 @@ struct Item {
 // per type, measured on the 4096 x 4096 droplet workload with the two-step
 // kernel: FP64 populations stream with non-temporal loads and stores (plain
 // stores cost 10 %); FP32 deviations use plain loads and stores (9 % faster
-// than non-temporal); FP32 storage with FP64 arithmetic shows no difference.
+// than non-temporal); FP32 storage with FP64 arithmetic and FP16 deviations
+// show no difference.
 struct f32s_f64a {};  // FP32 deviation storage with FP64 collision arithmetic
 template <typename S> struct Store;
 template <> struct Store<double> {
