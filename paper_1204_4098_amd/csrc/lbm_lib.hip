@@ -261,7 +261,9 @@ hipError_t launch_step2_t(const void* src, void* dst, const RunDev& d, int L,
                           const unsigned long long* base, unsigned long long local,
                           unsigned long long* flag, hipStream_t st) {
   const int SW = 64 * NW;
-  const int nstrips = (d.nx + SW - 7) / (SW - 6);  // strips of at most SW - 6 columns
+  // strips of at most SW - 6 columns after their edges are aligned down to A columns
+  constexpr int A = Step2Align<S>::value;
+  const int nstrips = (d.nx + SW - 7 - (A - 1)) / (SW - 6 - (A - 1));
   int grid;
   if (L > 0) {
     grid = nstrips * ((d.ny + L - 1) / L);
