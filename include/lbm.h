@@ -177,9 +177,10 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes);
  * 2) is how many rows of loads are in flight while a row is collided.
  * `steps` (1 or 2) is the number of time steps one launch advances: with 2,
  * the populations of the intermediate step stay on chip (registers and LDS),
- * so they cross HBM once per two steps; its strips are 64*waves - 6 columns
- * wide (the six extra columns are recomputed), waves in {4, 8}, and an odd
- * remainder of lbm_step(n) runs one single step.
+ * so they cross HBM once per two steps; its strips are at most
+ * 64*waves - 6 columns wide (the six extra columns are recomputed), spread
+ * evenly over nx (FP64: strip edges on 64-byte boundaries), waves in {4, 8},
+ * and an odd remainder of lbm_step(n) runs one single step.
  * waves in {1, 2, 4, 8, 16}; rows in [0, 128].  lbm_tune times the candidates
  * on the current state without advancing it and keeps the fastest per lattice
  * step; the choice is cached per (nx, ny, precision) for the life of the
