@@ -184,6 +184,26 @@ def test_two_step_edge_shapes(L, shape):
     assert max(errs) < TOL64, errs
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("nx", [243, 244, 250, 251, 486, 487, 493, 500])
+def test_two_step_strip_edges_bitwise(L, nx, precision):
+    # widths around the strip-count thresholds of the two-step kernel: a single
+    # 250-column strip (every lane of a 4-wave block busy), FP64 edges rounded to
+    # 64-byte boundaries, and 8-wave strips; against single steps, bit for bit
+    gp, _ = pair(L, nx, 9, t=0.8, tau=0.8, scheme=2, sigma=0.1, precision=precision)
+    rho0 = slab_rho(nx, 9, CS, 0.8, seed=nx)
+    outs = []
+    for tile in [(2, 8, 1), (4, 0, 2, 2), (4, 3, 1, 2), (8, 0, 2, 2)]:
+        lat = L.Lattice(gp, rho0)
+        lat.set_tile(*tile)
+        lat.step(11)
+        outs.append(lat.get_populations()[0])
+        assert lat.status()[0] == L.LBM_OK
+        lat.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_two_step_divergence_step(L):
     # the same divergence as test_divergence_step_matches_oracle, through two-step launches:
     # the step reported is the first one with a bad node, whichever half of a launch it is
