@@ -272,7 +272,7 @@ def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_s
         lat.tune()
     tile = list(lat.get_tile())
     if graph_steps:
-        lat.set_graph_steps(graph_steps)
+        lat.set_graph_steps(graph_steps)   # captures and uploads the graphs of both parities now
     lat.step(warmup)
     st, _, div = lat.status()
     if st != lbm.LBM_OK:
@@ -280,6 +280,7 @@ def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_s
         raise Diverged(div)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    captures = lat.graph_captures()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(lat.stream)
@@ -287,6 +288,8 @@ def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_s
     e1.record(lat.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if lat.graph_captures() != captures:
+        raise RuntimeError("a graph was captured inside the timed window")
     st, _, div = lat.status()
     lat.close()
     if st != lbm.LBM_OK:

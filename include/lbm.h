@@ -40,7 +40,10 @@
  * square root of Eq. (8), during a step marks the run as diverged: kernels
  * record the first such step on the device, and the next call that
  * synchronises (lbm_status, lbm_moments, lbm_mass, lbm_get_populations,
- * lbm_batch_coexistence) reports it.
+ * lbm_batch_coexistence, the lbm_batch_* accessors) reports it.  A diverged
+ * run is frozen: every later launch copies its stored populations unchanged,
+ * so the state read back is the one the diverging launch wrote, whatever the
+ * number of steps requested after it.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -190,9 +193,15 @@ int lbm_set_tile(lbm_ctx* c, int32_t waves, int32_t rows, int32_t depth, int32_t
 int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
 
 /* Replay n steps through captured HIP graphs of k steps each (k even, >= 2;
- * 0 disables).  Needs a non-null stream.  Results are bitwise identical to
- * eager launches. */
+ * 0 disables).  Needs a non-null stream.  The graphs of both buffer parities
+ * are captured, instantiated and uploaded by this call (and again by
+ * lbm_set_tile / lbm_tune when the tile changes), so lbm_step only replays
+ * them; synchronous.  Results are bitwise identical to eager launches. */
 int lbm_set_graph_steps(lbm_ctx* c, int32_t k);
+
+/* Number of graphs captured over the context's life (a tool can check that a
+ * timed lbm_step call captured none). */
+int lbm_graph_captures(lbm_ctx* c, int64_t* n);
 
 /* Raw device addresses of the two population buffers (for timing and
  * profiling tools) and which one holds the current state (0 or 1). */
@@ -212,12 +221,19 @@ int lbm_batch_init(int32_t nruns, const lbm_params* p, const double* const* rho0
                    void* dev_workspace, size_t ws_bytes, void* hip_stream, lbm_batch** out);
 int lbm_batch_step(lbm_batch* b, int64_t n);
 
-/* Coexistence densities of flat-interface runs: rho_l = mean density over y
- * of the column at x = nx/2, rho_g = the same at x = 0 (slab in [nx/4, 3nx/4)).
- * status[i] = LBM_OK or LBM_EDIVERGED; diverged_at[i] = first diverged step or
- * -1.  Arrays of nruns (nullable).  Synchronous. */
+/* Coexistence densities of flat-interface runs (Sec. IV.B, slab of Eq. 36
+ * with normal x): rho_l = mean density over y of the column at x = nx/2,
+ * rho_g = the same at x = 0 (slab in [nx/4, 3nx/4)).  Reduced on the device in
+ * FP64 by one launch over all runs (fixed summation order); only 2 doubles and
+ * the status per run cross to the host.  rho_l = rho_g = NaN for a diverged
+ * run.  status[i] = LBM_OK or LBM_EDIVERGED; diverged_at[i] = first diverged
+ * step or -1.  Arrays of nruns (nullable).  Synchronous. */
 int lbm_batch_coexistence(lbm_batch* b, double* rho_l, double* rho_g, int32_t* status,
                           int64_t* diverged_at);
+/* Moments (as lbm_moments) and FP64 populations (as lbm_get_populations) of
+ * one run; host arrays sized for that run.  Synchronous.  They return
+ * LBM_EDIVERGED, with the outputs filled from the frozen state, when the run
+ * has diverged. */
 int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double* vy, double* p);
 int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f);
 /* Tiles of the batch work list (rows = 0: one item per strip of up to 128
@@ -228,7 +244,9 @@ int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f);
 int lbm_batch_tune(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
 int lbm_batch_set_tile(lbm_batch* b, int32_t waves, int32_t rows, int32_t depth, int32_t steps);
 int lbm_batch_get_tile(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
+/* As lbm_set_graph_steps: captures the graphs of both parities now. */
 int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k);
+int lbm_batch_graph_captures(lbm_batch* b, int64_t* n);
 /* Lattice updates per step summed over runs that are still active. */
 int lbm_batch_nodes(lbm_batch* b, int64_t* nodes);
 int lbm_batch_destroy(lbm_batch* b);

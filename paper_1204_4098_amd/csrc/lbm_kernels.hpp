@@ -360,6 +360,23 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
   if (__ballot(bad) != 0 && __lane_id() == 0) atomicMin(flag, step);
 }
 
+// A run that diverged at an earlier launch is frozen: instead of a time step
+// its tiles copy the stored populations unchanged from src to dst, so both
+// buffers hold the state the diverging launch wrote, whatever the parity of
+// later launches.  Columns [x0, x0+ncols), rows [y0, y0+nrows), SW threads.
+template <typename S, int SW>
+__device__ __forceinline__ void copy_tile(const typename Store<S>::E* __restrict__ src,
+                                          typename Store<S>::E* __restrict__ dst, const RunDev& d,
+                                          int x0, int y0, int ncols, int nrows) {
+  if ((int)threadIdx.x >= ncols) return;
+  const int x = x0 + (int)threadIdx.x;
+  for (int j = 0; j < nrows; ++j) {
+    const int64_t o = (int64_t)(y0 + j) * d.pitch + x;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) dst[o + a * d.plane] = src[o + a * d.plane];
+  }
+}
+
 // XCD-aware block order: consecutive tiles go to the same XCD (blocks are
 // dispatched round-robin over the 8 XCDs), so halo rows/columns shared by
 // neighbouring tiles are found in that XCD's L2.
@@ -383,13 +400,16 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
   __shared__ double haloL[LMAX + 2], haloR[LMAX + 2];
   constexpr int SW = 64 * NW;
   const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
-  if (*flag < step) return;  // diverged at an earlier step: the run is frozen
+  const bool frozen = *flag < step;  // diverged at an earlier step
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   if (L > 0) {
     const int sy = t / nstrips, sx = t - sy * nstrips;
     const int x0 = sx * SW, y0 = sy * L;
-    tile_step<S, NW, PF>(src, dst, d, x0, y0, min(SW, d.nx - x0), min(L, d.ny - y0), step, flag,
-                         ring, haloL, haloR);
+    if (frozen)
+      copy_tile<S, SW>(src, dst, d, x0, y0, min(SW, d.nx - x0), min(L, d.ny - y0));
+    else
+      tile_step<S, NW, PF>(src, dst, d, x0, y0, min(SW, d.nx - x0), min(L, d.ny - y0), step, flag,
+                           ring, haloL, haloR);
     return;
   }
   const int64_t total = (int64_t)nstrips * d.ny;
@@ -400,7 +420,11 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
     int n = (int)min(e - r, (int64_t)(d.ny - y));
     n = min(n, LMAX);
     const int x0 = s * SW;
-    tile_step<S, NW, PF>(src, dst, d, x0, y, min(SW, d.nx - x0), n, step, flag, ring, haloL, haloR);
+    if (frozen)
+      copy_tile<S, SW>(src, dst, d, x0, y, min(SW, d.nx - x0), n);
+    else
+      tile_step<S, NW, PF>(src, dst, d, x0, y, min(SW, d.nx - x0), n, step, flag, ring, haloL,
+                           haloR);
     r += n;
     __syncthreads();  // LDS is reused by the next piece
   }
@@ -641,7 +665,7 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
   __shared__ double ring2[4][64 * NW];
   __shared__ R xch[6][64 * NW];
   const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
-  if (*flag < step) return;  // diverged at an earlier step: the run is frozen
+  const bool frozen = *flag < step;  // diverged at an earlier step
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   auto strip = [&](int sx, int& x0, int& nc) {
     constexpr int A = Step2Align<S>::value;
@@ -656,7 +680,11 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
     int x0, nc;
     strip(sx, x0, nc);
     const int y0 = sy * L;
-    tile_step2<S, NW, PF>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2, xch);
+    if (frozen)
+      copy_tile<S, 64 * NW>(src, dst, d, x0, y0, nc, min(L, d.ny - y0));
+    else
+      tile_step2<S, NW, PF>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2,
+                            xch);
     return;
   }
   const int64_t total = (int64_t)nstrips * d.ny;
@@ -683,7 +711,10 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
     }
     int x0, nc;
     strip(s, x0, nc);
-    tile_step2<S, NW, PF>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, xch);
+    if (frozen)
+      copy_tile<S, 64 * NW>(src, dst, d, x0, y, nc, n);
+    else
+      tile_step2<S, NW, PF>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, xch);
     r += n;
     __syncthreads();  // LDS is reused by the next piece
   }
@@ -707,16 +738,18 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step(const typename Store<S>:
   for (int i = lo + slot; i < hi; i += nb) {
     const Item it = items[i];
     const RunDev d = runs[it.run];
-    if (flags[it.run] < step) continue;
-    tile_step<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
-                         &flags[it.run], ring, haloL, haloR);
+    if (flags[it.run] < step)  // frozen run
+      copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows);
+    else
+      tile_step<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
+                           &flags[it.run], ring, haloL, haloR);
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
 // Persistent batched launch of two steps (tile_step2) over a work list whose
 // items are at most 64*NW - 6 columns wide.  A run frozen by divergence at an
-// earlier launch is skipped; grid must be a multiple of 8.
+// earlier launch is copied unchanged; grid must be a multiple of 8.
 template <typename S, int NW, int PF>
 __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>::E* __restrict__ src,
                                                          typename Store<S>::E* __restrict__ dst,
@@ -735,10 +768,54 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>
   for (int i = lo + slot; i < hi; i += nb) {
     const Item it = items[i];
     const RunDev d = runs[it.run];
-    if (flags[it.run] < step) continue;
-    tile_step2<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
-                          &flags[it.run], ring1, ring2, xch);
+    if (flags[it.run] < step)  // frozen run
+      copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows);
+    else
+      tile_step2<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
+                            &flags[it.run], ring1, ring2, xch);
     __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+// Coexistence densities of flat interfaces with normal x, for every run of a
+// batch: out[2r] = mean over y of rho at column nx/2 (liquid), out[2r+1] = the
+// same at column 0 (vapour), in FP64 with rho decoded as the step kernels do
+// (rho_ref + sum of the pulled populations).  One block per run; per-thread
+// partial sums over rows tid, tid+256, ... then a fixed-order tree, so the
+// result does not depend on timing.  A diverged run gives NaN.
+template <typename S>
+__global__ __launch_bounds__(256) void k_batch_coex(const typename Store<S>::E* __restrict__ pool,
+                                                    const RunDev* __restrict__ runs,
+                                                    const unsigned long long* __restrict__ flags,
+                                                    double* __restrict__ out) {
+  using R = typename Store<S>::R;
+  __shared__ double sl[256], sg[256];
+  const int r = blockIdx.x;
+  const RunDev d = runs[r];
+  const typename Store<S>::E* src = pool + d.off;
+  const Cols cl = cols_of(d.nx / 2, d.nx), cg = cols_of(0, d.nx);
+  double al = 0.0, ag = 0.0;
+  for (int y = threadIdx.x; y < d.ny; y += 256) {
+    R f[9];
+    pull9<S>(src, d, cl, y, f);
+    al += d.rho_ref + double(sum9(f));
+    pull9<S>(src, d, cg, y, f);
+    ag += d.rho_ref + double(sum9(f));
+  }
+  sl[threadIdx.x] = al;
+  sg[threadIdx.x] = ag;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      sl[threadIdx.x] += sl[threadIdx.x + k];
+      sg[threadIdx.x] += sg[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const bool div = flags[r] != ~0ull;
+    out[2 * r] = div ? __builtin_nan("") : sl[0] / d.ny;
+    out[2 * r + 1] = div ? __builtin_nan("") : sg[0] / d.ny;
   }
 }
 

@@ -416,6 +416,20 @@ hipError_t launch_mass(int prec, const void* src, const RunDev& d, long long* pi
   return hipGetLastError();
 }
 
+hipError_t launch_batch_coex(int prec, const void* pool, const RunDev* runs, int nruns,
+                             const unsigned long long* flags, double* out, hipStream_t st) {
+  const dim3 g(nruns), b(256);
+  if (prec == LBM_PREC_F64)
+    hipLaunchKernelGGL(k_batch_coex<double>, g, b, 0, st, (const double*)pool, runs, flags, out);
+  else if (prec == LBM_PREC_F32DEV)
+    hipLaunchKernelGGL(k_batch_coex<float>, g, b, 0, st, (const float*)pool, runs, flags, out);
+  else if (prec == LBM_PREC_F32DEV_F64)
+    hipLaunchKernelGGL(k_batch_coex<f32s_f64a>, g, b, 0, st, (const float*)pool, runs, flags, out);
+  else
+    hipLaunchKernelGGL(k_batch_coex<__half>, g, b, 0, st, (const __half*)pool, runs, flags, out);
+  return hipGetLastError();
+}
+
 // ---- tile heuristics and tuning cache -----------------------------------------
 
 Tile default_tile(int nx, int ny) {
@@ -459,6 +473,7 @@ struct lbm_ctx {
   int graph_k;
   hipGraphExec_t gexec[2];
   Tile gtile;
+  int64_t captures;  // graphs captured so far
 };
 
 namespace {
@@ -502,7 +517,6 @@ void drop_graphs(lbm_ctx* c) {
 }
 
 int upload_state(lbm_ctx* c, const std::vector<char>& raw, int64_t step) {
-  drop_graphs(c);
   HIPCHK(hipMemcpyAsync(c->buf[0], raw.data(), raw.size(), hipMemcpyHostToDevice, c->st));
   c->cur = 0;
   c->step = step;
@@ -532,11 +546,28 @@ int capture_graph(lbm_ctx* c, int parity) {
   if (e != hipSuccess || e2 != hipSuccess) return LBM_EHIP;
   e = hipGraphInstantiate(&c->gexec[parity], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
+  if (e == hipSuccess) e = hipGraphUpload(c->gexec[parity], c->st);
   if (e != hipSuccess) {
+    if (c->gexec[parity]) (void)hipGraphExecDestroy(c->gexec[parity]);
     c->gexec[parity] = nullptr;
     return LBM_EHIP;
   }
   c->gtile = c->tile;
+  ++c->captures;
+  return LBM_OK;
+}
+
+// Capture (or re-capture after a tile change) the graphs of both buffer
+// parities now, so that no later lbm_step call pays for a capture.
+int prepare_graphs(lbm_ctx* c) {
+  if (c->graph_k <= 0) return LBM_OK;
+  if (!same_tile(c->gtile, c->tile)) drop_graphs(c);
+  for (int parity = 0; parity < 2; ++parity)
+    if (!c->gexec[parity]) {
+      int st = capture_graph(c, parity);
+      if (st != LBM_OK) return st;
+    }
+  HIPCHK(hipStreamSynchronize(c->st));
   return LBM_OK;
 }
 
@@ -823,7 +854,7 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
 int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
   if (!c || !valid_tile(nw, L, depth, 16, steps)) return LBM_EINVAL;
   c->tile = Tile{nw, L, depth, steps};
-  return LBM_OK;
+  return prepare_graphs(c);
 }
 
 int lbm_get_tile(lbm_ctx* c, int32_t* nw, int32_t* L, int32_t* depth, int32_t* steps) {
@@ -875,6 +906,8 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, in
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[{c->p.nx, c->p.ny, c->p.precision, 0}] = bt;
   }
+  const int gst = prepare_graphs(c);
+  if (gst != LBM_OK) return gst;
   if (nw_out) *nw_out = bt.nw;
   if (L_out) *L_out = bt.L;
   if (depth_out) *depth_out = bt.pf;
@@ -887,6 +920,12 @@ int lbm_set_graph_steps(lbm_ctx* c, int32_t k) {
   if (k > 0 && c->st == nullptr) return LBM_EINVAL;  // the null stream cannot be captured
   drop_graphs(c);
   c->graph_k = k;
+  return prepare_graphs(c);
+}
+
+int lbm_graph_captures(lbm_ctx* c, int64_t* n) {
+  if (!c || !n) return LBM_EINVAL;
+  *n = c->captures;
   return LBM_OK;
 }
 
@@ -936,12 +975,14 @@ struct lbm_batch {
   int graph_k;
   hipGraphExec_t gexec[2];
   Tile gtile;
+  int64_t captures;  // graphs captured so far
+  double* coex;      // 2 * nruns doubles: (rho_l, rho_g) per run
 };
 
 namespace {
 
 struct BatchLayout {
-  size_t pool, runs, items, flags, aux, total;
+  size_t pool, runs, items, flags, aux, coex, total;
   int items_cap;
   size_t aux_nodes;
 };
@@ -968,7 +1009,8 @@ BatchLayout batch_layout(int n, const lbm_params* p) {
   L.flags = align_up((n + 1) * sizeof(unsigned long long));
   L.aux_nodes = maxn;
   L.aux = align_up(5 * maxn * sizeof(double));
-  L.total = 2 * L.pool + L.runs + L.items + L.flags + L.aux;
+  L.coex = align_up(2 * (size_t)n * sizeof(double));
+  L.total = 2 * L.pool + L.runs + L.items + L.flags + L.aux + L.coex;
   return L;
 }
 
@@ -1025,11 +1067,26 @@ int batch_capture(lbm_batch* b, int parity) {
   if (e != hipSuccess || e2 != hipSuccess) return LBM_EHIP;
   e = hipGraphInstantiate(&b->gexec[parity], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
+  if (e == hipSuccess) e = hipGraphUpload(b->gexec[parity], b->st);
   if (e != hipSuccess) {
+    if (b->gexec[parity]) (void)hipGraphExecDestroy(b->gexec[parity]);
     b->gexec[parity] = nullptr;
     return LBM_EHIP;
   }
   b->gtile = b->tile;
+  ++b->captures;
+  return LBM_OK;
+}
+
+int batch_prepare_graphs(lbm_batch* b) {
+  if (b->graph_k <= 0) return LBM_OK;
+  if (!same_tile(b->gtile, b->tile)) batch_drop_graphs(b);
+  for (int parity = 0; parity < 2; ++parity)
+    if (!b->gexec[parity]) {
+      int st = batch_capture(b, parity);
+      if (st != LBM_OK) return st;
+    }
+  HIPCHK(hipStreamSynchronize(b->st));
   return LBM_OK;
 }
 
@@ -1087,6 +1144,7 @@ int lbm_batch_init(int32_t n, const lbm_params* p, const double* const* rho0, vo
   b->ctr = b->flags + n;
   b->aux = reinterpret_cast<double*>(b->ws + 2 * Lay.pool + Lay.runs + Lay.items + Lay.flags);
   b->aux_nodes = Lay.aux_nodes;
+  b->coex = reinterpret_cast<double*>(b->ws + 2 * Lay.pool + Lay.runs + Lay.items + Lay.flags + Lay.aux);
   b->st = static_cast<hipStream_t>(stream);
   std::vector<char> pool(Lay.pool, 0);
   int64_t off = 0;
@@ -1183,7 +1241,8 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
 int lbm_batch_set_tile(lbm_batch* b, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
   if (!b || !valid_tile(nw, L, depth, 8, steps) || (L > 0 && L < 4)) return LBM_EINVAL;
   batch_drop_graphs(b);
-  return batch_items(b, Tile{nw, L, depth, steps});
+  const int st = batch_items(b, Tile{nw, L, depth, steps});
+  return st != LBM_OK ? st : batch_prepare_graphs(b);
 }
 
 int lbm_batch_get_tile(lbm_batch* b, int32_t* nw, int32_t* L, int32_t* depth, int32_t* steps) {
@@ -1200,6 +1259,12 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k) {
   if (k > 0 && b->st == nullptr) return LBM_EINVAL;
   batch_drop_graphs(b);
   b->graph_k = k;
+  return batch_prepare_graphs(b);
+}
+
+int lbm_batch_graph_captures(lbm_batch* b, int64_t* n) {
+  if (!b || !n) return LBM_EINVAL;
+  *n = b->captures;
   return LBM_OK;
 }
 
@@ -1246,6 +1311,8 @@ int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[batch_key(b)] = bt;
   }
+  st = batch_prepare_graphs(b);
+  if (st != LBM_OK) return st;
   if (nw_out) *nw_out = bt.nw;
   if (L_out) *L_out = bt.L;
   if (depth_out) *depth_out = bt.pf;
@@ -1265,6 +1332,14 @@ int lbm_batch_nodes(lbm_batch* b, int64_t* nodes) {
   return LBM_OK;
 }
 
+// LBM_EDIVERGED when the run is frozen by divergence, else LBM_OK (synchronises).
+static int batch_run_status(lbm_batch* b, int32_t run) {
+  unsigned long long f = 0;
+  HIPCHK(hipMemcpyAsync(&f, b->flags + run, sizeof f, hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  return f == kNoDiv ? LBM_OK : LBM_EDIVERGED;
+}
+
 int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double* vy, double* p) {
   if (!b || run < 0 || run >= b->nruns) return LBM_EINVAL;
   const RunDev& d = b->d[run];
@@ -1275,8 +1350,7 @@ int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double
   double* outs[4] = {rho, vx, vy, p};
   for (int i = 0; i < 4; ++i)
     if (outs[i]) HIPCHK(hipMemcpyAsync(outs[i], a + i * n, n * sizeof(double), hipMemcpyDeviceToHost, b->st));
-  HIPCHK(hipStreamSynchronize(b->st));
-  return LBM_OK;
+  return batch_run_status(b, run);
 }
 
 int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f) {
@@ -1285,37 +1359,27 @@ int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f) {
   std::vector<char> raw(raw_bytes_of(b->p[run]));
   const char* src = static_cast<const char*>(b->buf[b->cur]) + d.off * b->esize;
   HIPCHK(hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, b->st));
-  HIPCHK(hipStreamSynchronize(b->st));
+  const int st = batch_run_status(b, run);
+  if (st != LBM_OK && st != LBM_EDIVERGED) return st;
   decode_any(b->prec, b->p[run], d.rho_ref, raw.data(), f);
-  return LBM_OK;
+  return st;
 }
 
 int lbm_batch_coexistence(lbm_batch* b, double* rho_l, double* rho_g, int32_t* status,
                           int64_t* diverged_at) {
   if (!b) return LBM_EINVAL;
+  HIPCHK(launch_batch_coex(b->prec, b->buf[b->cur], b->d_runs, b->nruns, b->flags, b->coex, b->st));
   std::vector<unsigned long long> fl(b->nruns);
+  std::vector<double> lg(2 * (size_t)b->nruns);
   HIPCHK(hipMemcpyAsync(fl.data(), b->flags, b->nruns * sizeof(unsigned long long), hipMemcpyDeviceToHost, b->st));
+  HIPCHK(hipMemcpyAsync(lg.data(), b->coex, lg.size() * sizeof(double), hipMemcpyDeviceToHost, b->st));
   HIPCHK(hipStreamSynchronize(b->st));
-  std::vector<double> rho(b->aux_nodes);
   for (int r = 0; r < b->nruns; ++r) {
     const bool div = fl[r] != kNoDiv;
     if (status) status[r] = div ? LBM_EDIVERGED : LBM_OK;
     if (diverged_at) diverged_at[r] = div ? (int64_t)fl[r] : -1;
-    double l = NAN, g = NAN;
-    if (!div) {
-      int st = lbm_batch_moments(b, r, rho.data(), nullptr, nullptr, nullptr);
-      if (st != LBM_OK) return st;
-      const int nx = b->p[r].nx, ny = b->p[r].ny;
-      double sl = 0, sg = 0;
-      for (int y = 0; y < ny; ++y) {
-        sl += rho[(size_t)y * nx + nx / 2];
-        sg += rho[(size_t)y * nx];
-      }
-      l = sl / ny;
-      g = sg / ny;
-    }
-    if (rho_l) rho_l[r] = l;
-    if (rho_g) rho_g[r] = g;
+    if (rho_l) rho_l[r] = lg[2 * r];
+    if (rho_g) rho_g[r] = lg[2 * r + 1];
   }
   return LBM_OK;
 }

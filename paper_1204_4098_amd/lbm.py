@@ -62,10 +62,11 @@ _SIGS = {
     "lbm_state_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "lbm_save_state": (C.c_int, [_vp, _vp, C.c_size_t]),
     "lbm_load_state": (C.c_int, [_vp, _vp, C.c_size_t]),
-    "lbm_tune": (C.c_int, [_vp, _ip, _ip, _ip]),
-    "lbm_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
-    "lbm_get_tile": (C.c_int, [_vp, _ip, _ip, _ip]),
+    "lbm_tune": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
+    "lbm_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "lbm_get_tile": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     "lbm_set_graph_steps": (C.c_int, [_vp, C.c_int32]),
+    "lbm_graph_captures": (C.c_int, [_vp, _lp]),
     "lbm_device_buffers": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), _ip]),
     "lbm_destroy": (C.c_int, [_vp]),
     "lbm_batch_workspace_bytes": (C.c_int, [C.c_int32, _P, C.POINTER(C.c_size_t)]),
@@ -78,6 +79,7 @@ _SIGS = {
     "lbm_batch_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "lbm_batch_get_tile": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     "lbm_batch_set_graph_steps": (C.c_int, [_vp, C.c_int32]),
+    "lbm_batch_graph_captures": (C.c_int, [_vp, _lp]),
     "lbm_batch_nodes": (C.c_int, [_vp, _lp]),
     "lbm_batch_destroy": (C.c_int, [_vp]),
 }
@@ -260,7 +262,13 @@ class Lattice:
         return w.value, r.value, d.value, k.value
 
     def set_graph_steps(self, k: int):
+        """Replay steps through graphs of k steps (captured now, both parities)."""
         _check(lib().lbm_set_graph_steps(self.ctx, int(k)), "lbm_set_graph_steps")
+
+    def graph_captures(self) -> int:
+        n = C.c_int64()
+        _check(lib().lbm_graph_captures(self.ctx, C.byref(n)), "lbm_graph_captures")
+        return n.value
 
     def device_buffers(self):
         b0, b1, cur = _vp(), _vp(), C.c_int32()
@@ -315,16 +323,22 @@ class Batch:
                                            dv.ctypes.data), "lbm_batch_coexistence")
         return rl, rg, st, dv
 
-    def moments(self, run: int):
+    def moments(self, run: int, check=True):
+        """(rho, vx, vy, p) of one run; check=False also returns the frozen state
+        of a diverged run instead of raising."""
         q = self.ps[run]
         out = [np.empty((q.ny, q.nx)) for _ in range(4)]
-        _check(lib().lbm_batch_moments(self.b, int(run), *[o.ctypes.data for o in out]), "lbm_batch_moments")
+        st = lib().lbm_batch_moments(self.b, int(run), *[o.ctypes.data for o in out])
+        if check or st not in (LBM_OK, LBM_EDIVERGED):
+            _check(st, "lbm_batch_moments")
         return tuple(out)
 
-    def get_populations(self, run: int):
+    def get_populations(self, run: int, check=True):
         q = self.ps[run]
         f = np.empty((9, q.ny, q.nx))
-        _check(lib().lbm_batch_get_populations(self.b, int(run), f.ctypes.data), "lbm_batch_get_populations")
+        st = lib().lbm_batch_get_populations(self.b, int(run), f.ctypes.data)
+        if check or st not in (LBM_OK, LBM_EDIVERGED):
+            _check(st, "lbm_batch_get_populations")
         return f
 
     def tune(self):
@@ -345,6 +359,11 @@ class Batch:
 
     def set_graph_steps(self, k: int):
         _check(lib().lbm_batch_set_graph_steps(self.b, int(k)), "lbm_batch_set_graph_steps")
+
+    def graph_captures(self) -> int:
+        n = C.c_int64()
+        _check(lib().lbm_batch_graph_captures(self.b, C.byref(n)), "lbm_batch_graph_captures")
+        return n.value
 
     def nodes(self) -> int:
         n = C.c_int64()

@@ -307,3 +307,44 @@ def test_divergence_is_reported(L):
     with pytest.raises(L.LbmError) as e:
         L.Lattice(gp, bad)
     assert e.value.status == L.LBM_EPSI
+
+
+def test_graphs_are_captured_before_stepping(L):
+    # set_graph_steps captures both parities at once; later steps only replay them,
+    # and a tile change recaptures at set_tile, not inside lbm_step
+    gp, _ = pair(L, 128, 64, t=0.8, tau=1.0, scheme=2, sigma=0.1)
+    rho0 = slab_rho(128, 64, CS, 0.8, seed=5)
+    lat = L.Lattice(gp, rho0)
+    assert lat.graph_captures() == 0
+    lat.set_graph_steps(10)
+    assert lat.graph_captures() == 2
+    lat.step(3)
+    lat.step(47)
+    assert lat.graph_captures() == 2
+    lat.set_tile(4, 0, 2, 2)
+    assert lat.graph_captures() == 4
+    lat.step(40)
+    assert lat.graph_captures() == 4 and lat.status()[:2] == (L.LBM_OK, 90)
+    lat.close()
+
+
+@pytest.mark.parametrize("tile", [(1, 16, 2), (4, 0, 2, 2)])
+def test_diverged_run_stays_frozen(L, tile):
+    # after the step that diverged, further launches copy the state unchanged: the
+    # populations read back do not depend on how many more steps were asked for
+    gp, _ = pair(L, 96, 80, t=0.6, tau=1.0, scheme=2, sigma=0.105, eos=PR)
+    from oracle import thermo as th
+    import synth
+    c = th.maxwell_pr(0.6)
+    rho0 = synth.droplet(96, 80, c.rho_l, c.rho_g, 20, 4.0, 0.005)
+    lat = L.Lattice(gp, rho0)
+    lat.set_tile(*tile)
+    lat.step(200)
+    st, _, d = lat.status()
+    assert st == L.LBM_EDIVERGED and 0 <= d < 200
+    snaps = []
+    for extra in (0, 1, 1, 2, 3):
+        lat.step(extra)
+        snaps.append(lat.save_state()[56:])   # raw storage after the header
+    assert all(s == snaps[0] for s in snaps[1:])
+    lat.close()

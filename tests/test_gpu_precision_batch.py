@@ -248,3 +248,47 @@ def test_full_size_droplets4096_sampled(L, prec, tol):
     errs = list(_window_check(L, lat, op, 4096, 4096, pts))
     assert max(errs) < tol, errs
     lat.close()
+
+
+@pytest.mark.parametrize("steps", [0, 300])
+def test_batch_coexistence_kernel_vs_oracle(L, steps):
+    # the device reduction of rho_l / rho_g against the oracle's column means of
+    # the same runs: at step 0 the fields are identical (1e-14), after 300 steps
+    # they agree to the FP64 parity bound
+    gps, ops, rhos = _batch_runs(L)
+    b = L.Batch(gps, rhos)
+    b.set_tile(4, 8, 2)
+    b.step(steps)
+    rl, rg, st, dv = b.coexistence()
+    assert np.all(st == 0) and np.all(dv == -1)
+    tol = 1e-14 if steps == 0 else 1e-10
+    for i, (op, r) in enumerate(zip(ops, rhos)):
+        f = olbm.init_equilibrium(r)
+        assert olbm.step(op, f, steps)[0] == 0
+        ref = olbm.moments(op, f)[0]
+        nx = r.shape[1]
+        assert abs(rl[i] / ref[:, nx // 2].mean() - 1) < tol, i
+        assert abs(rg[i] / ref[:, 0].mean() - 1) < tol, i
+    b.close()
+
+
+def test_batch_diverged_run_is_frozen_and_reported(L):
+    gps, _, rhos = _batch_runs(L)
+    gp_bad, _ = pair(L, 96, 80, t=0.6, tau=1.0, scheme=2, sigma=0.105, eos=PR)
+    c = th.maxwell_pr(0.6)
+    bad = synth.droplet(96, 80, c.rho_l, c.rho_g, 20, 4.0, 0.005)
+    b = L.Batch(gps + [gp_bad], rhos + [bad])
+    b.set_tile(4, 0, 2, 2)
+    b.step(300)
+    rl, rg, st, _ = b.coexistence()
+    assert st[-1] == L.LBM_EDIVERGED and np.isnan(rl[-1]) and np.isnan(rg[-1])
+    with pytest.raises(L.LbmError) as e:
+        b.get_populations(len(gps))
+    assert e.value.status == L.LBM_EDIVERGED
+    snaps = []
+    for extra in (0, 1, 2, 3):
+        b.step(extra)
+        snaps.append(b.get_populations(len(gps), check=False))
+    for s in snaps[1:]:
+        assert np.array_equal(s, snaps[0], equal_nan=True)
+    b.close()

@@ -458,3 +458,28 @@ def test_laplace_law_droplets():
     r2 = 1 - res[0] / ((y - y.mean()) ** 2).sum()
     assert slope > 0 and r2 > 0.999
     assert abs(icpt) < 0.05 * y.max()
+
+
+def test_actual_velocity_vanishes_at_flat_interface_equilibrium():
+    # Table I: the actual fluid velocity is v = u + F/(2 rho).  At the steady state of a
+    # flat interface, Eq. (32) makes the mass flux rho v constant across the interface,
+    # and zero total momentum makes it zero, while u = -F/(2 rho) is not.  After 8000
+    # steps (noise-free slab, improved scheme) max|rho v| / max|F/2| is ~1e-9 here; the
+    # term with its sign flipped would give ~2, with a factor 2 (v = u + F/rho) ~1.
+    Tc, _ = th.critical_cs()
+    c = th.maxwell_cs(0.8)
+    nx, ny = 64, 4
+    rho0 = synth.slab(nx, ny, c.rho_l, c.rho_g, 16, 48, 2.0, 0.0, synth.BASE_SEED)
+    op = lbm.Params(nx=nx, ny=ny, tau=1.0, T=0.8 * Tc, sigma=0.1)
+    f = lbm.init_equilibrium(rho0)
+    assert lbm.step(op, f, 8000) == (lbm.OK, -1)
+    rho, vx, vy, p = lbm.moments(op, f)
+    psi = np.sqrt(2.0 * (p - rho / 3.0) / op.G)
+    Fx, Fy = lbm.interaction_force(op, psi)
+    assert np.abs(Fx).max() > 1e-2 and np.abs(Fy).max() < 1e-12
+    assert np.abs(rho * vx).max() / np.abs(Fx / 2).max() < 1e-6
+    assert np.abs(vy).max() < 1e-12
+    # the velocity of the populations alone, u = v - F/(2 rho), carries the force term
+    jx = (f * EX[:, None, None]).sum(0)
+    assert np.allclose(vx, jx / rho + Fx / (2 * rho), rtol=0, atol=1e-15)
+    assert np.abs(jx).max() > 0.5 * np.abs(Fx / 2).max()

@@ -3,6 +3,7 @@ rounding, GELU and Adam against their definitions."""
 import math
 
 import numpy as np
+import pytest
 
 import synth
 from oracle import mlp
@@ -79,3 +80,20 @@ def test_training_decreases_loss():
         l, g = mlp.loss_and_grad(th, X, T, norm)
         th, m, v = mlp.adam(th, m, v, g, t, lr=3e-3)
     assert l < 0.2 * l0
+
+
+@pytest.mark.parametrize("t", [2, 3, 10])
+def test_adam_bias_correction_beyond_the_first_step(t):
+    # with a constant gradient g, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the
+    # bias-corrected step is lr * g / (|g| + eps) at every t.  A bias correction with
+    # t - 1, or b1 and b2 swapped, or without the square root, fails at t >= 2.
+    g = np.array([1.0, -2.0, 0.5, 1e-3, -1e-3])
+    th = np.zeros(5)
+    m = np.zeros(5)
+    v = np.zeros(5)
+    for k in range(1, t + 1):
+        new, m, v = mlp.adam(th, m, v, g, k, lr=0.01)
+        assert np.allclose(new - th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+        th = new
+    assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-14)
+    assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-14)

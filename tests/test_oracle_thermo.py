@@ -187,3 +187,60 @@ def test_fig4_ratio_rises_steeply_unpinned_values():
     ratio65 = r65.rho_l / r65.rho_g
     assert 100 < ratio70 < 140
     assert ratio65 / ratio70 > 10
+
+
+def test_pr_alpha_reproduces_the_acentric_factor():
+    # The acentric factor is defined by the reduced saturation pressure at T/Tc = 0.7:
+    # omega = -log10(p_sat(0.7 Tc) / p_c) - 1, and the Peng-Robinson kappa(omega) of
+    # alpha(T) = [1 + kappa (1 - sqrt(T/Tc))]^2 is fitted so that the EOS reproduces it.
+    # The oracle's Maxwell p0 at 0.7 Tc with the configured omega = 0.344 gives 0.3451
+    # (0.3 % off).  A wrong sign of the omega term (-0.365) or of the omega^2 term
+    # (0.392), alpha left unsquared, or T/Tc in place of sqrt(T/Tc) all land far
+    # outside 0.5 %; each is planted below.
+    eos = th.pr_default()
+    Tc = eos.Tc
+    rc = th.critical_point_pr_rho(eos)
+    pc = eos.p(rc, Tc)
+    omega = float(eos.omega)
+
+    def omega_of(e):
+        c = th.maxwell_area(e, mp.mpf("0.7") * Tc)
+        return float(-mp.log10(mp.mpf(c.p0) / pc) - 1)
+
+    assert abs(omega_of(eos) / omega - 1) < 5e-3
+    # planted mistakes in alpha(T) must fail the same bound
+    w = eos.omega
+    for kappa in (mp.mpf("0.37464") - mp.mpf("1.54226") * w - mp.mpf("0.26992") * w**2,
+                  mp.mpf("0.37464") + mp.mpf("1.54226") * w + mp.mpf("0.26992") * w**2):
+        bad = th.PengRobinson()
+        bad.kappa, bad._Tc = kappa, Tc
+        assert abs(omega_of(bad) / omega - 1) > 5e-3
+
+    class NotSquared(th.PengRobinson):
+        def alpha(self, T):
+            return 1 + self.kappa * (1 - mp.sqrt(T / self.Tc))
+
+    class LinearInT(th.PengRobinson):
+        def alpha(self, T):
+            s = 1 + self.kappa * (1 - T / self.Tc)
+            return s * s
+
+    for cls in (NotSquared, LinearInT):
+        bad = cls()
+        bad._Tc = Tc
+        assert abs(omega_of(bad) / omega - 1) > 5e-3, cls.__name__
+
+
+def test_c_oracle_peng_robinson_equals_the_analysis_oracle():
+    # the C oracle's Peng-Robinson branch (the pressure the LB oracle's psi uses) against
+    # the mpmath Peng-Robinson above, pointwise over both phases and three temperatures
+    from oracle import lbm as olbm
+    eos = th.pr_default()
+    Tc = float(eos.Tc)
+    for t in (0.6, 0.8, 0.95):
+        op = olbm.Params(nx=3, ny=3, eos=olbm.EOS_PR, a=2 / 49, b=2 / 21, R=1.0, omega=0.344,
+                         T=t * Tc, Tc=Tc)
+        for rho in (1e-3, 0.0102, 0.5, 2.657, 6.0, 8.72, 10.0):
+            ref = eos.p(mp.mpf(rho), mp.mpf(t * Tc))
+            got = olbm.p_eos(op, rho)
+            assert abs(got - float(ref)) <= 1e-13 * max(abs(float(ref)), 1e-3 * rho), (t, rho, got, ref)
