@@ -903,12 +903,15 @@ __device__ __forceinline__ double decode(__half v, int a, double rref) {
   return double(__half2float(v)) + wr;
 }
 
-// Mass: per block, sum of round-to-nearest-even(rho * 2^40) (exact, int64) and
-// the FP64 sum; rho = sum_a f_a in direction order of the decoded populations.
+// Mass: per block, sum of round-to-nearest-even(rho * 2^40) (exact, 128-bit)
+// and the FP64 sum; rho = sum_a f_a in direction order of the decoded
+// populations.  A thread's int64 sum holds at most ceil(nodes / (blocks * 256))
+// terms, 8192 for 2^31 nodes and 1024 blocks, so it cannot overflow for
+// densities below 1000; the block sums are 128-bit.
 template <typename S>
 __global__ __launch_bounds__(256) void k_mass(const typename Store<S>::E* __restrict__ src, RunDev d,
-                                              long long* part_i, double* part_d) {
-  __shared__ long long si[256];
+                                              __int128* part_i, double* part_d) {
+  __shared__ __int128 si[256];
   __shared__ double sd[256];
   const int64_t n = (int64_t)d.nx * d.ny;
   long long acc_i = 0;
@@ -941,6 +944,22 @@ __global__ __launch_bounds__(256) void k_mass(const typename Store<S>::E* __rest
     part_i[blockIdx.x] = si[0];
     part_d[blockIdx.x] = sd[0];
   }
+}
+
+// Final mass sums over the block partials, in block order (one thread):
+// out[0], out[1] = low and high 64-bit words of the 128-bit integer sum, out[2]
+// = the bits of the FP64 sum.
+__global__ void k_mass_final(const __int128* __restrict__ part_i, const double* __restrict__ part_d,
+                             int nblocks, unsigned long long* __restrict__ out) {
+  __int128 acc = 0;
+  double m = 0.0;
+  for (int i = 0; i < nblocks; ++i) {
+    acc += part_i[i];
+    m += part_d[i];
+  }
+  out[0] = (unsigned long long)acc;
+  out[1] = (unsigned long long)(acc >> 64);
+  out[2] = __double_as_longlong(m);
 }
 
 }  // namespace lbm

@@ -403,8 +403,10 @@ hipError_t launch_moments(int prec, const void* src, const RunDev& d, double* rh
   return launch_moments_s<__half>(src, d, rho, vx, vy, p, psi, st);
 }
 
-hipError_t launch_mass(int prec, const void* src, const RunDev& d, long long* pi, double* pd,
-                       hipStream_t st) {
+// Mass partials of kMassBlocks work-groups into part_i/part_d, then the final
+// sums into out[0..2] (see k_mass_final).
+hipError_t launch_mass(int prec, const void* src, const RunDev& d, __int128* pi, double* pd,
+                       unsigned long long* out, hipStream_t st) {
   if (prec == LBM_PREC_F64)
     hipLaunchKernelGGL(k_mass<double>, dim3(kMassBlocks), dim3(256), 0, st, (const double*)src, d, pi, pd);
   else if (prec == LBM_PREC_F32DEV)
@@ -413,8 +415,14 @@ hipError_t launch_mass(int prec, const void* src, const RunDev& d, long long* pi
     hipLaunchKernelGGL(k_mass<f32s_f64a>, dim3(kMassBlocks), dim3(256), 0, st, (const float*)src, d, pi, pd);
   else
     hipLaunchKernelGGL(k_mass<__half>, dim3(kMassBlocks), dim3(256), 0, st, (const __half*)src, d, pi, pd);
+  hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(1), 0, st, (const __int128*)pi, (const double*)pd,
+                     kMassBlocks, out);
   return hipGetLastError();
 }
+
+// Bytes of mass scratch: 128-bit and FP64 partials per work-group, then the
+// three result words.
+constexpr size_t kMassScratch = kMassBlocks * (sizeof(__int128) + sizeof(double)) + 4 * sizeof(unsigned long long);
 
 hipError_t launch_batch_coex(int prec, const void* pool, const RunDev* runs, int nruns,
                              const unsigned long long* flags, double* out, hipStream_t st) {
@@ -463,8 +471,9 @@ struct lbm_ctx {
   void* buf[2];
   int cur;
   double* aux;  // 5 planes of nx*ny doubles: rho, vx, vy, p, psi
-  long long* part_i;
+  __int128* part_i;   // mass scratch: partials and the result words
   double* part_d;
+  unsigned long long* mass_out;
   unsigned long long* flag;
   unsigned long long* ctr;
   hipStream_t st;
@@ -486,7 +495,7 @@ size_t raw_bytes_of(const lbm_params& p) {
 size_t ctx_layout(const lbm_params& p, size_t* pop, size_t* aux, size_t* parts, size_t* misc) {
   *pop = align_up(raw_bytes_of(p));
   *aux = align_up(5 * (size_t)p.nx * p.ny * sizeof(double));
-  *parts = align_up(kMassBlocks * (sizeof(long long) + sizeof(double)));
+  *parts = align_up(kMassScratch);
   *misc = align_up(2 * sizeof(unsigned long long));
   return 2 * *pop + *aux + *parts + *misc;
 }
@@ -661,8 +670,9 @@ int lbm_init(const lbm_params* p, const double* rho0, const double* ux0, const d
   c->buf[0] = c->ws;
   c->buf[1] = c->ws + pop;
   c->aux = reinterpret_cast<double*>(c->ws + 2 * pop);
-  c->part_i = reinterpret_cast<long long*>(c->ws + 2 * pop + aux);
-  c->part_d = reinterpret_cast<double*>(c->ws + 2 * pop + aux + kMassBlocks * sizeof(long long));
+  c->part_i = reinterpret_cast<__int128*>(c->ws + 2 * pop + aux);
+  c->part_d = reinterpret_cast<double*>(c->part_i + kMassBlocks);
+  c->mass_out = reinterpret_cast<unsigned long long*>(c->part_d + kMassBlocks);
   c->flag = reinterpret_cast<unsigned long long*>(c->ws + 2 * pop + aux + parts);
   c->ctr = c->flag + 1;
   c->st = static_cast<hipStream_t>(stream);
@@ -771,25 +781,22 @@ int lbm_flat_profile(lbm_ctx* c, double* rho_bar, double* p_n) {
   return lbm_status(c, nullptr, nullptr);
 }
 
+// The three result words of the mass kernels into the caller's outputs.
+static void mass_words(const unsigned long long w[3], int64_t* fixed, double* mass) {
+  if (fixed) {
+    fixed[0] = (int64_t)w[0];
+    fixed[1] = (int64_t)w[1];
+  }
+  if (mass) std::memcpy(mass, &w[2], sizeof(double));
+}
+
 int lbm_mass(lbm_ctx* c, int64_t* fixed, double* mass) {
   if (!c) return LBM_EINVAL;
-  HIPCHK(launch_mass(c->p.precision, c->buf[c->cur], c->d, c->part_i, c->part_d, c->st));
-  std::vector<long long> pi(kMassBlocks);
-  std::vector<double> pd(kMassBlocks);
-  HIPCHK(hipMemcpyAsync(pi.data(), c->part_i, kMassBlocks * sizeof(long long), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipMemcpyAsync(pd.data(), c->part_d, kMassBlocks * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(launch_mass(c->p.precision, c->buf[c->cur], c->d, c->part_i, c->part_d, c->mass_out, c->st));
+  unsigned long long w[3];
+  HIPCHK(hipMemcpyAsync(w, c->mass_out, sizeof w, hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
-  __int128 acc = 0;
-  double m = 0.0;
-  for (int i = 0; i < kMassBlocks; ++i) {
-    acc += pi[i];
-    m += pd[i];
-  }
-  if (fixed) {
-    fixed[0] = (int64_t)(uint64_t)(unsigned __int128)acc;
-    fixed[1] = (int64_t)(acc >> 64);
-  }
-  if (mass) *mass = m;
+  mass_words(w, fixed, mass);
   return lbm_status(c, nullptr, nullptr);
 }
 
