@@ -203,6 +203,10 @@ int lbm_set_graph_steps(lbm_ctx* c, int32_t k);
  * timed lbm_step call captured none). */
 int lbm_graph_captures(lbm_ctx* c, int64_t* n);
 
+/* The context's parameters, with rho_ref resolved (the mean initial density
+ * when NaN was given; 0 for FP64 storage). */
+int lbm_get_params(lbm_ctx* c, lbm_params* out);
+
 /* Raw device addresses of the two population buffers (for timing and
  * profiling tools) and which one holds the current state (0 or 1). */
 int lbm_device_buffers(lbm_ctx* c, void** buf0, void** buf1, int32_t* current);

@@ -424,6 +424,7 @@ hipError_t launch_mass(int prec, const void* src, const RunDev& d, __int128* pi,
 // three result words.
 constexpr size_t kMassScratch = kMassBlocks * (sizeof(__int128) + sizeof(double)) + 4 * sizeof(unsigned long long);
 
+
 hipError_t launch_batch_coex(int prec, const void* pool, const RunDev* runs, int nruns,
                              const unsigned long long* flags, double* out, hipStream_t st) {
   const dim3 g(nruns), b(256);
@@ -933,6 +934,12 @@ int lbm_set_graph_steps(lbm_ctx* c, int32_t k) {
 int lbm_graph_captures(lbm_ctx* c, int64_t* n) {
   if (!c || !n) return LBM_EINVAL;
   *n = c->captures;
+  return LBM_OK;
+}
+
+int lbm_get_params(lbm_ctx* c, lbm_params* out) {
+  if (!c || !out) return LBM_EINVAL;
+  *out = c->p;
   return LBM_OK;
 }
 

@@ -68,6 +68,7 @@ _SIGS = {
     "lbm_set_graph_steps": (C.c_int, [_vp, C.c_int32]),
     "lbm_graph_captures": (C.c_int, [_vp, _lp]),
     "lbm_device_buffers": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), _ip]),
+    "lbm_get_params": (C.c_int, [_vp, _P]),
     "lbm_destroy": (C.c_int, [_vp]),
     "lbm_batch_workspace_bytes": (C.c_int, [C.c_int32, _P, C.POINTER(C.c_size_t)]),
     "lbm_batch_init": (C.c_int, [C.c_int32, _P, C.POINTER(_vp), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
@@ -269,6 +270,15 @@ class Lattice:
         n = C.c_int64()
         _check(lib().lbm_graph_captures(self.ctx, C.byref(n)), "lbm_graph_captures")
         return n.value
+
+    def params(self) -> lbm_params:
+        """The context's parameters (rho_ref resolved to the value in use)."""
+        out = lbm_params()
+        _check(lib().lbm_get_params(self.ctx, C.byref(out)), "lbm_get_params")
+        return out
+
+    def rho_ref(self) -> float:
+        return self.params().rho_ref
 
     def device_buffers(self):
         b0, b1, cur = _vp(), _vp(), C.c_int32()
