@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1, 2, 3])
     ap.add_argument("--t-over-tc", type=float, default=None)
     ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--settle-ms", type=float, default=100.0,
+                    help="untimed stepping before the warm-up, so the timed steps see sustained clocks")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="batched,precision,droplet1024,slab64",
@@ -180,7 +182,7 @@ def main():
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     nx, ny, rho0, kw, cfg = workload(args.workload, args.t_over_tc)
     res = time_lattice(lbm, torch, nx, ny, rho0, kw, args.precision, args.steps, args.warmup,
-                       args.graph_steps, not args.no_tune, tile)
+                       args.graph_steps, not args.no_tune, tile, args.settle_ms)
     bpl = BYTES_PER_LUP[args.precision]
     ts = res["tile"][3]                      # time steps per launch of the step kernel
     launch_ms = res["kernel_ms"] * ts        # average duration of one launch
@@ -200,7 +202,7 @@ def main():
         "dtype": PREC_NAME[args.precision],
         "data": "synthetic",
         "config": dict(cfg, precision=PREC_NAME[args.precision], tile=res["tile"],
-                       graph_steps=args.graph_steps),
+                       graph_steps=args.graph_steps, settle_ms=args.settle_ms),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_for(args.workload, args.precision, res["tile"]),
@@ -217,7 +219,7 @@ def main():
         out["precision"] = {}
         for prec in (1, 2, 3):
             r = time_lattice(lbm, torch, nx, ny, rho0, kw, prec, args.steps, args.warmup,
-                             args.graph_steps, not args.no_tune)
+                             args.graph_steps, not args.no_tune, settle_ms=args.settle_ms)
             gbs = BYTES_PER_LUP[prec] * nx * ny / (r["kernel_ms"] * r["tile"][3] * 1e-3) / 1e9
             out["precision"][PREC_NAME[prec]] = {"mlups": round(r["mlups"], 1), "tile": r["tile"],
                                                  "achieved_gbs": round(gbs, 1),
@@ -262,8 +264,26 @@ class Diverged(RuntimeError):
         self.step = step
 
 
-def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_steps, tune, tile=None):
-    """Warm up, then time `steps` steps between a device sync on both sides."""
+def settle(lat, torch, ms):
+    """Step the lattice untimed for about `ms` milliseconds of GPU time, so that the
+    timed steps run at the GPU's sustained clocks: a kernel trace of the FP64 droplet
+    workload shows launches 4-12 after a start from idle running up to 33 % slower
+    (528 -> 698 us per launch) and recovering only after ~40 launches (~520 us)."""
+    if ms <= 0:
+        return
+    t0 = time.perf_counter()
+    n = 0
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        lat.step(20)
+        torch.cuda.synchronize()
+        n += 20
+    return n
+
+
+def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_steps, tune, tile=None,
+                 settle_ms=100.0):
+    """Settle, warm up, then time `steps` steps between a device sync on both sides.
+    The settling steps and the warm-up steps advance the state but are not timed."""
     p = lbm.params(nx, ny, precision=precision, **kw)
     lat = lbm.Lattice(p, rho0, device="cuda:0")
     if tile:
@@ -273,6 +293,7 @@ def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_s
     tile = list(lat.get_tile())
     if graph_steps:
         lat.set_graph_steps(graph_steps)   # captures and uploads the graphs of both parities now
+    settle(lat, torch, settle_ms)
     lat.step(warmup)
     st, _, div = lat.status()
     if st != lbm.LBM_OK:

@@ -27,7 +27,8 @@ class _Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("tau", C.c_double), ("G", C.c_double),
                 ("eos", C.c_int32), ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
                 ("T", C.c_double), ("omega", C.c_double), ("Tc", C.c_double),
-                ("scheme", C.c_int32), ("sigma", C.c_double)]
+                ("scheme", C.c_int32), ("sigma", C.c_double), ("mrt", C.c_int32),
+                ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double)]
 
 
 @dataclass
@@ -45,10 +46,15 @@ class Params:
     Tc: float = 0.0
     scheme: int = SCHEME_IMPROVED
     sigma: float = 0.0
+    mrt: int = 0            # 1: multiple-relaxation-time collision (improved scheme only)
+    s_e: float = 1.0
+    s_eps: float = 1.0
+    s_q: float = 1.0
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.tau, self.G, self.eos, self.a, self.b, self.R,
-                       self.T, self.omega, self.Tc, self.scheme, self.sigma)
+                       self.T, self.omega, self.Tc, self.scheme, self.sigma, self.mrt, self.s_e,
+                       self.s_eps, self.s_q)
 
 
 _lib = None
@@ -78,6 +84,10 @@ def lib():
         L.or_mass.argtypes = [C.c_int32, C.c_int32, _dp, C.POINTER(C.c_double),
                               C.POINTER(C.c_int64)]
         L.or_mass.restype = None
+        L.or_mrt_row.argtypes = [C.c_int, C.c_int]; L.or_mrt_row.restype = C.c_double
+        L.or_mrt_collide.argtypes = [P, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, _dp]
+        L.or_mrt_collide.restype = None
         _lib = L
     return _lib
 
@@ -90,6 +100,19 @@ def psi(p: Params, rho: float):
     out = C.c_double()
     st = lib().or_psi(C.byref(p.c()), rho, C.byref(out))
     return out.value if st == OK else None
+
+
+def mrt_matrix() -> np.ndarray:
+    """The 9 x 9 moment matrix of the MRT collision (rows = moments)."""
+    return np.array([[lib().or_mrt_row(k, a) for a in range(9)] for k in range(9)])
+
+
+def mrt_collide(p: Params, f9, rho, ux, uy, Fx, Fy, psi2) -> np.ndarray:
+    """Post-collision populations of one node under the MRT collision."""
+    out = np.zeros(9)
+    lib().or_mrt_collide(C.byref(p.c()), np.ascontiguousarray(f9, dtype=np.float64), rho, ux, uy,
+                         Fx, Fy, psi2, out)
+    return out
 
 
 def feq(rho: float, ux: float, uy: float) -> np.ndarray:

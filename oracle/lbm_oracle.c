@@ -63,6 +63,11 @@ typedef struct {
   double Tc;        /* critical temperature, Peng-Robinson alpha(T) only */
   int32_t scheme;   /* OR_SCHEME_* */
   double sigma;     /* constant of the improved scheme, Eq. (31) */
+  /* Collision: 0 = BGK (Eq. 1); 1 = multiple relaxation times (see or_mrt_collide),
+   * with rates s_e (energy), s_eps (energy square) and s_q (energy flux); the
+   * density, momentum and stress moments relax at 1/tau. */
+  int32_t mrt;
+  double s_e, s_eps, s_q;
 } or_params;
 
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -208,8 +213,97 @@ void or_forcing(const or_params* p, double rho, double ux, double uy, double Fx,
   }
 }
 
+/* ---- multiple-relaxation-time collision -------------------------------------
+ * The paper states that the improved scheme extends to the MRT form of the
+ * model (Sec. IV.B, last paragraph) without writing it out.  This is the D2Q9
+ * MRT collision of Lallemand and Luo (Phys. Rev. E 61, 6546, 2000): moments
+ * m = M f with the rows (for e of squared length e2)
+ *   rho: 1;  e: -4 + 3 e2;  eps: 4 - (21/2) e2 + (9/2) e2^2;
+ *   j_x: ex;  q_x: (-5 + 3 e2) ex;  j_y: ey;  q_y: (-5 + 3 e2) ey;
+ *   p_xx: ex^2 - ey^2;  p_xy: ex ey,
+ * relaxed one by one, m* = m - s_k (m - m_eq) + (1 - s_k/2) S_k, f* = M^-1 m*.
+ * Reading of "readily extended": the equilibrium moments are M f_eq of Eq. (2)
+ * at v = u + F/(2 rho), and the source S is M applied to Eq. (31)'s bracket
+ * (the forcing term without its factor 1 - 1/(2 tau)), taken for moment k with
+ * the modified velocity v'_k = v + sigma F / ((1/s_k - 1/2) psi^2), i.e. with
+ * the moment's own relaxation time in place of tau.  With every rate equal to
+ * 1/tau this is the BGK improved scheme exactly. */
+
+/* Row k of the moment matrix at direction a (the polynomials above). */
+double or_mrt_row(int k, int a) {
+  double ex = EX[a], ey = EY[a], e2 = ex * ex + ey * ey;
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return -4.0 + 3.0 * e2;
+    case 2: return 4.0 - 10.5 * e2 + 4.5 * e2 * e2;
+    case 3: return ex;
+    case 4: return (-5.0 + 3.0 * e2) * ex;
+    case 5: return ey;
+    case 6: return (-5.0 + 3.0 * e2) * ey;
+    case 7: return ex * ex - ey * ey;
+    default: return ex * ey;
+  }
+}
+
+/* Relaxation rate of moment k. */
+static double mrt_rate(const or_params* p, int k) {
+  switch (k) {
+    case 1: return p->s_e;
+    case 2: return p->s_eps;
+    case 4: case 6: return p->s_q;
+    default: return 1.0 / p->tau;
+  }
+}
+
+/* Eq. (31)'s bracket w [(e - v')/c_s^2 + (e.v') e/c_s^4] . F at every direction. */
+static void improved_bracket(double vpx, double vpy, double Fx, double Fy, double* out) {
+  for (int a = 0; a < 9; ++a) {
+    double ev = EX[a] * vpx + EY[a] * vpy;
+    double cx = (EX[a] - vpx) / CS2 + ev * EX[a] / (CS2 * CS2);
+    double cy = (EY[a] - vpy) / CS2 + ev * EY[a] / (CS2 * CS2);
+    out[a] = WEQ[a] * (cx * Fx + cy * Fy);
+  }
+}
+
+/* One MRT collision of the populations f9 at a node (improved scheme). */
+void or_mrt_collide(const or_params* p, const double* f9, double rho, double ux, double uy,
+                    double Fx, double Fy, double psi2, double* out9) {
+  double vx = ux + Fx / (2.0 * rho), vy = uy + Fy / (2.0 * rho);
+  double feq[9], m[9], meq[9], ms[9], D[9];
+  or_feq(rho, vx, vy, feq);
+  for (int k = 0; k < 9; ++k) {
+    double sk = mrt_rate(p, k);
+    double vpx = vx + p->sigma * Fx / ((1.0 / sk - 0.5) * psi2);
+    double vpy = vy + p->sigma * Fy / ((1.0 / sk - 0.5) * psi2);
+    double br[9];
+    improved_bracket(vpx, vpy, Fx, Fy, br);
+    double S = 0.0;
+    m[k] = meq[k] = D[k] = 0.0;
+    for (int a = 0; a < 9; ++a) {
+      double Mka = or_mrt_row(k, a);
+      m[k] += Mka * f9[a];
+      meq[k] += Mka * feq[a];
+      S += Mka * br[a];
+      D[k] += Mka * Mka;
+    }
+    ms[k] = m[k] - sk * (m[k] - meq[k]) + (1.0 - sk / 2.0) * S;
+  }
+  /* the rows are orthogonal, so M^-1 = M^T diag(1 / |row k|^2) */
+  for (int a = 0; a < 9; ++a) {
+    double v = 0.0;
+    for (int k = 0; k < 9; ++k) v += or_mrt_row(k, a) * ms[k] / D[k];
+    out9[a] = v;
+  }
+}
+
 static int valid_params(const or_params* p) {
   if (p->nx < 3 || p->ny < 3) return 0;
+  if (p->mrt) {
+    if (p->scheme != OR_SCHEME_IMPROVED) return 0;
+    if (!(p->s_e > 0.0 && p->s_e < 2.0) || !(p->s_eps > 0.0 && p->s_eps < 2.0) ||
+        !(p->s_q > 0.0 && p->s_q < 2.0))
+      return 0;
+  }
   if (!(p->tau > 0.5)) return 0;
   if (p->eos != OR_EOS_CS && p->eos != OR_EOS_PR) return 0;
   if (p->scheme < OR_SCHEME_SC || p->scheme > OR_SCHEME_LADD) return 0;
@@ -279,6 +373,12 @@ int or_step(const or_params* p, double* f, int64_t nsteps, int64_t* diverged_at)
     for (size_t i = 0; i < n; ++i) {
       double f9[9], feq[9], Fa[9], ueqx, ueqy;
       for (int a = 0; a < 9; ++a) f9[a] = f[(size_t)a * n + i];
+      if (p->mrt) {
+        double out9[9];
+        or_mrt_collide(p, f9, rho[i], ux[i], uy[i], Fx[i], Fy[i], psi[i] * psi[i], out9);
+        for (int a = 0; a < 9; ++a) fs[(size_t)a * n + i] = out9[a];
+        continue;
+      }
       or_forcing(p, rho[i], ux[i], uy[i], Fx[i], Fy[i], psi[i] * psi[i], &ueqx, &ueqy, Fa);
       or_feq(rho[i], ueqx, ueqy, feq);
       for (int a = 0; a < 9; ++a)

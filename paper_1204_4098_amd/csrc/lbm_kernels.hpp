@@ -53,7 +53,12 @@ struct RunDev {
   // (w0, w1, w2 = 4/9, 1/9, 1/36)
   double wCe0, wCe1, wCe2, wBe3_1, wBe3_2;
   double rho_ref;           // deviation reference density (0 for FP64 storage)
-  int32_t run, pad;
+  int32_t run;
+  int32_t mrt;              // 1: multiple-relaxation-time collision (collide_mrt)
+  // MRT rates of the energy, energy-square and energy-flux moments (the others
+  // relax at inv_tau) and the improved scheme's sigma / (1/s - 1/2) for the
+  // energy and energy-square moments (sig above is the stress moments' value)
+  double s_e, s_eps, s_q, sig_e, sig_eps;
 };
 
 // A tile of the batched launch.
@@ -251,6 +256,84 @@ __device__ __forceinline__ void collide(R (&s)[9], R drho, R rho, R jx, R jy, R 
   collide_pair(s[6], s[8], wy - wx, Fy - Fx, vy - vx, w2, wr3_2, wCe2, wBe3_2, rho, drho, usq, vF3, om);
 }
 
+// Multiple-relaxation-time collision with the improved forcing scheme, on the
+// D2Q9 moments of Lallemand and Luo (2000): rho, e, eps, j_x, q_x, j_y, q_y,
+// p_xx, p_xy (squared row norms 9, 36, 36, 6, 12, 6, 12, 4, 4).  Each moment
+// relaxes at its own rate toward the moments of the Eq. (2) equilibrium at
+// v = u + F/(2 rho),
+//   e_eq = rho(-2 + 3|v|^2), eps_eq = rho(1 - 3|v|^2), q_eq = -rho v,
+//   p_xx,eq = rho(vx^2 - vy^2), p_xy,eq = rho vx vy,
+// and receives (1 - s/2) times the moment of Eq. (31)'s bracket taken with the
+// moment's own modified velocity v' = v + sigma F / ((1/s - 1/2) psi^2):
+//   S_e = 6 v'.F, S_eps = -6 v'.F, S_q = -F, S_xx = 2(v'x Fx - v'y Fy), S_xy = v'x Fy + v'y Fx.
+// The conserved moments need no relaxation: rho' = rho and j' = j + F (any
+// momentum rate gives this).  In deviation storage the moments of w rho_ref,
+// rho_ref (1, -2, 1, 0, ...), are taken out of rho, e and eps.  With every rate
+// 1/tau this is the BGK update of collide() up to rounding.
+template <typename R>
+__device__ __forceinline__ void collide_mrt(R (&s)[9], R drho, R rho, R jx, R jy, R Fx, R Fy,
+                                            R inv_psi2, const RunDev& d) {
+#pragma clang fp contract(off)
+  const R inv_rho = rcp(rho);
+  const R vx = fma(R(0.5) * Fx, inv_rho, jx * inv_rho), vy = fma(R(0.5) * Fy, inv_rho, jy * inv_rho);
+  const R v2 = fma(vx, vx, vy * vy), vF = fma(vx, Fx, vy * Fy);
+  const R FF = fma(Fx, Fx, Fy * Fy) * inv_psi2;
+  // moments of the stored values
+  const R ax = s[1] + s[3], ay = s[2] + s[4], a = ax + ay;
+  const R dg = (s[5] + s[7]) + (s[6] + s[8]);
+  const R e = fma(R(-4), s[0], fma(R(2), dg, -a));
+  const R ep = fma(R(4), s[0], fma(R(-2), a, dg));
+  const R qx = fma(R(-2), s[1] - s[3], (s[5] - s[7]) + (s[8] - s[6]));
+  const R qy = fma(R(-2), s[2] - s[4], (s[5] - s[7]) + (s[6] - s[8]));
+  const R pxx = ax - ay;
+  const R pxy = (s[5] + s[7]) - (s[6] + s[8]);
+  // equilibria (deviation form: rho_ref (1, -2, 1) removed from rho, e, eps)
+  const R r3v2 = R(3) * rho * v2;
+  const R e_eq = fma(R(-2), drho, r3v2), ep_eq = drho - r3v2;
+  const R se = R(d.s_e), sp = R(d.s_eps), sq = R(d.s_q), sn = R(d.inv_tau);
+  const R S_e = R(6) * fma(R(d.sig_e), FF, vF);
+  const R S_ep = R(-6) * fma(R(d.sig_eps), FF, vF);
+  const R sgn = R(2) * R(d.sig) * inv_psi2;
+  const R S_xx = fma(R(2), fma(vx, Fx, -(vy * Fy)), sgn * fma(Fx, Fx, -(Fy * Fy)));
+  const R S_xy = fma(vx, Fy, vy * Fx) + sgn * (Fx * Fy);
+  // m' = m - s (m - m_eq) + (1 - s/2) S
+  const R e1 = fma(-se, e - e_eq, e) + (R(1) - R(0.5) * se) * S_e;
+  const R ep1 = fma(-sp, ep - ep_eq, ep) + (R(1) - R(0.5) * sp) * S_ep;
+  const R hq = R(1) - R(0.5) * sq;
+  const R qx1 = fma(-sq, fma(rho, vx, qx), qx) - hq * Fx;
+  const R qy1 = fma(-sq, fma(rho, vy, qy), qy) - hq * Fy;
+  const R hn = R(1) - R(0.5) * sn;
+  const R pxx1 = fma(-sn, pxx - rho * fma(vx, vx, -(vy * vy)), pxx) + hn * S_xx;
+  const R pxy1 = fma(-sn, pxy - (rho * vx) * vy, pxy) + hn * S_xy;
+  const R jx1 = jx + Fx, jy1 = jy + Fy;
+  // back to populations: f = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m'
+  const R r0 = drho * R(1.0 / 9.0), r1 = e1 * R(1.0 / 36.0), r2 = ep1 * R(1.0 / 36.0);
+  const R r3 = jx1 * R(1.0 / 6.0), r4 = qx1 * R(1.0 / 12.0), r5 = jy1 * R(1.0 / 6.0),
+          r6 = qy1 * R(1.0 / 12.0), r7 = pxx1 * R(0.25), r8 = pxy1 * R(0.25);
+  s[0] = fma(R(4), r2 - r1, r0);
+  const R A = fma(R(-2), r2, r0 - r1), Dg = fma(R(2), r1, r0 + r2);
+  const R ox = fma(R(-2), r4, r3), oy = fma(R(-2), r6, r5);
+  s[1] = (A + ox) + r7;
+  s[3] = (A - ox) + r7;
+  s[2] = (A + oy) - r7;
+  s[4] = (A - oy) - r7;
+  const R X = r3 + r4, Y = r5 + r6;
+  s[5] = (Dg + (X + Y)) + r8;
+  s[6] = (Dg - (X - Y)) - r8;
+  s[7] = (Dg - (X + Y)) + r8;
+  s[8] = (Dg + (X - Y)) - r8;
+}
+
+// The collision of a node: BGK (collide) or MRT (collide_mrt).
+template <bool MRT, typename R>
+__device__ __forceinline__ void collide_any(R (&s)[9], R drho, R rho, R jx, R jy, R Fx, R Fy,
+                                            R inv_psi2, const RunDev& d) {
+  if constexpr (MRT)
+    collide_mrt<R>(s, drho, rho, jx, jy, Fx, Fy, inv_psi2, d);
+  else
+    collide<R>(s, drho, rho, jx, jy, Fx, Fy, inv_psi2, d);
+}
+
 template <typename R>
 __device__ __forceinline__ R mom_x(const R (&s)[9]) {
   return ((s[1] - s[3]) + (s[5] - s[7])) + (s[8] - s[6]);
@@ -265,7 +348,7 @@ __device__ __forceinline__ R mom_y(const R (&s)[9]) {
 // haloL/haloR [LMAX+2].  PF is the number of rows whose loads are in flight
 // while a row is collided: with PF = 2 the loads of row y+2 are issued before
 // the psi of row y+1 is evaluated and row y is collided.
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT = false>
 __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict__ src,
                                           typename Store<S>::E* __restrict__ dst,
                                           const RunDev& d, int x0, int y0, int ncols, int nrows,
@@ -343,7 +426,7 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
       const double rho64 = rref + double(drho);
       bad |= !(psi2c > 0.0) || !(rho64 > 0.0);
       const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
-      collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
+      collide_any<MRT, R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
       typename T::E* row = dst + (int64_t)y * d.pitch;
 #pragma unroll
       for (int a = 0; a < 9; ++a) T::st(row + a * d.plane + cx.x, fc[a]);
@@ -389,7 +472,7 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // balanced schedule, the strip-major row space [0, nstrips*ny) is split evenly
 // over the grid (sized to the resident capacity) and each block marches its
 // share in pieces of at most LMAX rows.
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT = false>
 __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __restrict__ src,
                                                   typename Store<S>::E* __restrict__ dst,
                                                   RunDev d, int L, int nstrips,
@@ -408,7 +491,7 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
     if (frozen)
       copy_tile<S, SW>(src, dst, d, x0, y0, min(SW, d.nx - x0), min(L, d.ny - y0));
     else
-      tile_step<S, NW, PF>(src, dst, d, x0, y0, min(SW, d.nx - x0), min(L, d.ny - y0), step, flag,
+      tile_step<S, NW, PF, MRT>(src, dst, d, x0, y0, min(SW, d.nx - x0), min(L, d.ny - y0), step, flag,
                            ring, haloL, haloR);
     return;
   }
@@ -423,7 +506,7 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
     if (frozen)
       copy_tile<S, SW>(src, dst, d, x0, y, min(SW, d.nx - x0), n);
     else
-      tile_step<S, NW, PF>(src, dst, d, x0, y, min(SW, d.nx - x0), n, step, flag, ring, haloL,
+      tile_step<S, NW, PF, MRT>(src, dst, d, x0, y, min(SW, d.nx - x0), n, step, flag, ring, haloL,
                            haloR);
     r += n;
     __syncthreads();  // LDS is reused by the next piece
@@ -489,14 +572,16 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   bool bad1 = false, bad2 = false;
   const int ya = y0 - 3;                            // first psi(t) row
 
-  // preload: psi(t) of rows y0-3 (ring slot 0) and y0-2 (slot 1); pulled row y0-2
-  R fc[9] = {}, fn[9] = {};
+  // preload: psi(t) of rows y0-3 (ring slot 0) and y0-2 (slot 1); pulled row y0-2,
+  // and with PF >= 2 the rows after it whose loads lead the march
+  R fc[9] = {}, fn[9] = {}, f2[9] = {};
   double psi2c = 0.0;
   if (act0) {
     R f[9];
     pull9<S>(src, d, cx, wrapy(ya), f);
     pull9<S>(src, d, cx, wrapy(ya + 1), fc);
-    if (PF == 2) pull9<S>(src, d, cx, wrapy(ya + 2), fn);
+    if (PF >= 2) pull9<S>(src, d, cx, wrapy(ya + 2), fn);
+    if (PF == 3) pull9<S>(src, d, cx, wrapy(ya + 3), f2);
     ring1[0][tid] = sqrt(psi2_of(rref + double(sum9(f)), d));
     psi2c = psi2_of(rref + double(sum9(fc)), d);
     ring1[1][tid] = sqrt(psi2c);
@@ -525,7 +610,9 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
       // the row loads go out at raised wave priority, so a wave about to issue
       // them is not held behind the other wave's arithmetic (FP64: 1 % faster)
       __builtin_amdgcn_s_setprio(2);
-      if (PF == 2) {
+      if (PF == 3) {
+        if (St || j + 2 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 3), fnn);
+      } else if (PF == 2) {
         if (St || j + 1 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 2), fnn);
       } else {
         pull9<S>(src, d, cx, wrapy(y1 + 1), fn);
@@ -585,6 +672,16 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
 #pragma unroll
         for (int a = 0; a < 9; ++a) fn[a] = fnn[a];
       }
+      if (PF == 3) {
+        if (St || j + 1 < n_one) {
+#pragma unroll
+          for (int a = 0; a < 9; ++a) fn[a] = f2[a];
+        }
+        if (St || j + 2 < n_one) {
+#pragma unroll
+          for (int a = 0; a < 9; ++a) f2[a] = fnn[a];
+        }
+      }
     }
     __syncthreads();
     // ---- phase 3: step-two collide of row r = q-1 and store
@@ -618,16 +715,19 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   // compiler): with U = 3, the period of the kept-row rotations (gA -> gB ->
   // gC, fnn -> fn -> fc), those rotations become register renaming instead of
   // moves.
+  // The steady rows end where the row loads PF - 1 rows ahead would pass the
+  // last step-one row.
   constexpr int U = SteadyUnroll<S>::value;
+  const int js_end = n_one - (PF == 3 ? 2 : 1);
   int js = 5;
-  for (; js + U <= n_one - 1; js += U) {
+  for (; js + U <= js_end; js += U) {
     row(js, Steady{});
     if constexpr (U > 1) row(js + 1, Steady{});
     if constexpr (U > 2) row(js + 2, Steady{});
   }
   if constexpr (U > 1)
-    for (; js < n_one - 1; ++js) row(js, Steady{});
-  for (int j = max(5, n_one - 1); j < n_one + 1; ++j) row(j, Edge{});
+    for (; js < js_end; ++js) row(js, Steady{});
+  for (int j = max(5, js_end); j < n_one + 1; ++j) row(j, Edge{});
   // divergence: the first step that saw a bad node (one atomic per wave)
   const auto b1 = __ballot(bad1), b2 = __ballot(bad2);
   if (__lane_id() == 0 && (b1 | b2) != 0) atomicMin(flag, b1 != 0 ? step : step + 1);
@@ -722,7 +822,7 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
 
 // Persistent batched step: blocks of XCD k walk the k-th contiguous eighth of
 // the work list.  Grid must be a multiple of 8.
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT = false>
 __global__ __launch_bounds__(64 * NW) void k_batch_step(const typename Store<S>::E* __restrict__ src,
                                                         typename Store<S>::E* __restrict__ dst,
                                                         const RunDev* __restrict__ runs,
@@ -741,7 +841,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step(const typename Store<S>:
     if (flags[it.run] < step)  // frozen run
       copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows);
     else
-      tile_step<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
+      tile_step<S, NW, PF, MRT>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
                            &flags[it.run], ring, haloL, haloR);
     __syncthreads();  // LDS is reused by the next item
   }

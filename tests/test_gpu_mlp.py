@@ -64,20 +64,22 @@ def test_gradient_matches_oracle(M):
     loss, g = net.gradient(X, T)
     rl, rg = omlp.loss_and_grad(th.astype(np.float64), X.astype(np.float64), T.astype(np.float64), n64)
     assert abs(loss / rl - 1) < 1e-4
-    # element by element, each entry against the largest entry of its block: the
+    # element by element, each entry against the largest entry of its block.  The
     # kernels accumulate in FP32 and round FP32 (not FP64) pre-activations and
     # errors to bfloat16, so a product whose operand straddles a bfloat16 rounding
-    # boundary differs by one bfloat16 ulp (2^-8 relative) from the oracle's; such
-    # outliers are allowed, counted, up to 1 % of a block
+    # boundary can differ by one bfloat16 ulp (2^-8 relative) from the oracle's.
+    # Measured on MI355X: block maxima 1.6e-7 .. 7.6e-6 and no entry above 2e-5;
+    # the bound allows 1 % of a block above 2e-5 (rounding-boundary outliers)
+    # and none above 1e-4.
     for name, shape in omlp.SHAPES:
         a = omlp.unpack(g)[name]
         b = omlp.unpack(rg)[name]
         err = np.abs(a - b) / np.abs(b).max()
-        out = int(np.sum(err > 2e-4))
+        out = int(np.sum(err > 2e-5))
         print(f"{name}: max {err.max():.2e}, p99 {np.quantile(err, 0.99):.2e}, "
-              f"median {np.median(err):.2e}, {out} of {err.size} above 2e-4", flush=True)
-        assert err.max() < 4e-3, (name, err.max())
-        assert out <= max(1, err.size // 100), (name, out)
+              f"median {np.median(err):.2e}, {out} of {err.size} above 2e-5", flush=True)
+        assert err.max() < 1e-4, (name, err.max())
+        assert out <= err.size // 100, (name, out)
     # deterministic: the same call gives the same bits
     loss2, g2 = net.gradient(X, T)
     assert loss2 == loss and np.array_equal(g, g2)
