@@ -161,6 +161,23 @@ int lbm_flat_profile(lbm_ctx* c, double* rho_bar, double* p_n);
  * to FP64 first); *mass = FP64 sum.  Either pointer may be NULL.  Synchronous. */
 int lbm_mass(lbm_ctx* c, int64_t* fixed, double* mass);
 
+/* Allocation-free variant of lbm_mass, for callers that cannot allocate
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  It needs no context or workspace: dev_populations is a
+ * population buffer in the library's storage layout (as lbm_device_buffers
+ * returns it; nx, ny, precision and, for deviation storage, rho_ref as in the
+ * lbm_params that made it; rho_ref is ignored for FP64).  Outputs as lbm_mass,
+ * bit for bit.  The work-group partials live in a static device array of
+ * 24,608 bytes that every GPU the library runs on holds until the process
+ * ends; each call overwrites it entirely, so calls that overlap on one GPU
+ * (two streams or threads at once) race.  Calls no allocator: two kernels,
+ * one 24-byte copy to the host and a synchronisation of hip_stream (NULL = the
+ * null stream).  nx, ny >= 3 and nx*ny <= LBM_NOALLOC_MAX_NODES, else
+ * LBM_EINVAL (shape, precision, rho_ref) or LBM_ENOSPACE (too many nodes). */
+#define LBM_NOALLOC_MAX_NODES 2147483647LL
+int lbm_mass_noalloc(const void* dev_populations, int32_t nx, int32_t ny, int32_t precision,
+                     double rho_ref, void* hip_stream, int64_t* fixed, double* mass);
+
 /* Current populations f_a(x, t) decoded to FP64, host array 9*ny*nx [a][y][x]. */
 int lbm_get_populations(lbm_ctx* c, double* f, int64_t* step);
 

@@ -424,6 +424,40 @@ hipError_t launch_mass(int prec, const void* src, const RunDev& d, __int128* pi,
 // three result words.
 constexpr size_t kMassScratch = kMassBlocks * (sizeof(__int128) + sizeof(double)) + 4 * sizeof(unsigned long long);
 
+}  // namespace
+}  // namespace lbm
+
+// Device scratch of lbm_mass_noalloc (the mass partials and result words,
+// kMassScratch = 24,608 bytes), one copy per GPU, held until the process ends.
+// Host code never uses this name as an address: it uses the per-device
+// pointer hipGetSymbolAddress returned for it.
+static __device__ __align__(256) unsigned char scratch[lbm::kMassScratch];
+
+namespace lbm {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];  // device address of `scratch` per device (null until set up)
+
+// The current device's address of `scratch`, looked up on the first call on
+// that device (with it current) and kept.
+hipError_t scratch_of_current_device(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch[dev]);
+  return hipSuccess;
+}
 
 hipError_t launch_batch_coex(int prec, const void* pool, const RunDev* runs, int nruns,
                              const unsigned long long* flags, double* out, hipStream_t st) {
@@ -799,6 +833,32 @@ int lbm_mass(lbm_ctx* c, int64_t* fixed, double* mass) {
   HIPCHK(hipStreamSynchronize(c->st));
   mass_words(w, fixed, mass);
   return lbm_status(c, nullptr, nullptr);
+}
+
+int lbm_mass_noalloc(const void* dev_populations, int32_t nx, int32_t ny, int32_t precision,
+                     double rho_ref, void* hip_stream, int64_t* fixed, double* mass) {
+  if (!dev_populations || nx < 3 || ny < 3) return LBM_EINVAL;
+  if (precision < LBM_PREC_F64 || precision > LBM_PREC_F32DEV_F64 || !std::isfinite(rho_ref))
+    return LBM_EINVAL;
+  if ((int64_t)nx * ny > LBM_NOALLOC_MAX_NODES) return LBM_ENOSPACE;
+  char* base = nullptr;
+  HIPCHK(scratch_of_current_device(&base));
+  RunDev d{};
+  d.nx = nx;
+  d.ny = ny;
+  d.pitch = pitch_of(nx);
+  d.plane = plane_of(nx, ny, esize_of(precision));
+  d.rho_ref = precision == LBM_PREC_F64 ? 0.0 : rho_ref;
+  __int128* pi = reinterpret_cast<__int128*>(base);
+  double* pd = reinterpret_cast<double*>(pi + kMassBlocks);
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(pd + kMassBlocks);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  HIPCHK(launch_mass(precision, dev_populations, d, pi, pd, out, st));
+  unsigned long long w[3];
+  HIPCHK(hipMemcpyAsync(w, out, sizeof w, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  mass_words(w, fixed, mass);
+  return LBM_OK;
 }
 
 int lbm_get_populations(lbm_ctx* c, double* f, int64_t* step) {

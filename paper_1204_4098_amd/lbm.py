@@ -56,6 +56,7 @@ _SIGS = {
     "lbm_moments": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_moments_device": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_mass": (C.c_int, [_vp, _lp, _dp]),
+    "lbm_mass_noalloc": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, _vp, _lp, _dp]),
     "lbm_flat_profile": (C.c_int, [_vp, _vp, _vp]),
     "lbm_get_populations": (C.c_int, [_vp, _vp, _lp]),
     "lbm_set_populations": (C.c_int, [_vp, _vp, C.c_int64]),
