@@ -216,6 +216,21 @@ int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth, int3
  * them; synchronous.  Results are bitwise identical to eager launches. */
 int lbm_set_graph_steps(lbm_ctx* c, int32_t k);
 
+/* Collision operator.  rates = NULL: BGK (Eq. 1, the default).  Otherwise the
+ * D2Q9 multiple-relaxation-time collision of Lallemand and Luo (Phys. Rev. E
+ * 61, 6546, 2000) with the improved forcing scheme carried into moment space,
+ * the extension the paper names at the end of Sec. IV.B: rates[0..2] = s_e,
+ * s_eps, s_q, the relaxation rates of the energy, energy-square and energy-flux
+ * moments (each in (0, 2)); density, momentum and stress relax at 1/tau, so
+ * the shear viscosity stays c_s^2 (tau - 1/2) and the bulk viscosity becomes
+ * c_s^2 (1/s_e - 1/2).  Each moment gets Eq. (31)'s forcing moment with
+ * v' = v + sigma F / ((1/s - 1/2) psi^2) for its own rate s, so rates all equal
+ * to 1/tau give the BGK improved scheme.  Improved scheme only, FP64 or FP32
+ * deviation storage (else LBM_ENOTSUP); one time step per launch (a two-step
+ * tile becomes the same tile with one step; lbm_set_tile with steps = 2 then
+ * returns LBM_ENOTSUP).  Captured graphs are rebuilt. */
+int lbm_set_mrt(lbm_ctx* c, const double* rates);
+
 /* Number of graphs captured over the context's life (a tool can check that a
  * timed lbm_step call captured none). */
 int lbm_graph_captures(lbm_ctx* c, int64_t* n);

@@ -572,16 +572,14 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   bool bad1 = false, bad2 = false;
   const int ya = y0 - 3;                            // first psi(t) row
 
-  // preload: psi(t) of rows y0-3 (ring slot 0) and y0-2 (slot 1); pulled row y0-2,
-  // and with PF >= 2 the rows after it whose loads lead the march
-  R fc[9] = {}, fn[9] = {}, f2[9] = {};
+  // preload: psi(t) of rows y0-3 (ring slot 0) and y0-2 (slot 1); pulled row y0-2
+  R fc[9] = {}, fn[9] = {};
   double psi2c = 0.0;
   if (act0) {
     R f[9];
     pull9<S>(src, d, cx, wrapy(ya), f);
     pull9<S>(src, d, cx, wrapy(ya + 1), fc);
-    if (PF >= 2) pull9<S>(src, d, cx, wrapy(ya + 2), fn);
-    if (PF == 3) pull9<S>(src, d, cx, wrapy(ya + 3), f2);
+    if (PF == 2) pull9<S>(src, d, cx, wrapy(ya + 2), fn);
     ring1[0][tid] = sqrt(psi2_of(rref + double(sum9(f)), d));
     psi2c = psi2_of(rref + double(sum9(fc)), d);
     ring1[1][tid] = sqrt(psi2c);
@@ -610,9 +608,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
       // the row loads go out at raised wave priority, so a wave about to issue
       // them is not held behind the other wave's arithmetic (FP64: 1 % faster)
       __builtin_amdgcn_s_setprio(2);
-      if (PF == 3) {
-        if (St || j + 2 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 3), fnn);
-      } else if (PF == 2) {
+      if (PF == 2) {
         if (St || j + 1 < n_one) pull9<S>(src, d, cx, wrapy(y1 + 2), fnn);
       } else {
         pull9<S>(src, d, cx, wrapy(y1 + 1), fn);
@@ -672,16 +668,6 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
 #pragma unroll
         for (int a = 0; a < 9; ++a) fn[a] = fnn[a];
       }
-      if (PF == 3) {
-        if (St || j + 1 < n_one) {
-#pragma unroll
-          for (int a = 0; a < 9; ++a) fn[a] = f2[a];
-        }
-        if (St || j + 2 < n_one) {
-#pragma unroll
-          for (int a = 0; a < 9; ++a) f2[a] = fnn[a];
-        }
-      }
     }
     __syncthreads();
     // ---- phase 3: step-two collide of row r = q-1 and store
@@ -715,10 +701,10 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   // compiler): with U = 3, the period of the kept-row rotations (gA -> gB ->
   // gC, fnn -> fn -> fc), those rotations become register renaming instead of
   // moves.
-  // The steady rows end where the row loads PF - 1 rows ahead would pass the
-  // last step-one row.
+  // The steady rows end where the row loads one row ahead would pass the last
+  // step-one row.
   constexpr int U = SteadyUnroll<S>::value;
-  const int js_end = n_one - (PF == 3 ? 2 : 1);
+  const int js_end = n_one - 1;
   int js = 5;
   for (; js + U <= js_end; js += U) {
     row(js, Steady{});
@@ -987,6 +973,33 @@ __global__ void k_normal_pressure(const double* __restrict__ rbar, RunDev d, dou
   const double G = -d.mG;
   pn[x] = rbar[x] * (1.0 / 3.0) + 0.5 * G * pc * pc + (G / 12.0) * (3.0 * pc * d2) +
           2.0 * G * G * sigma * d1 * d1;
+}
+
+// Surface tension of one interface of a periodic flat slab with normal x, from
+// the column-mean profile: gamma = (kappa + 2 G^2 sigma) sum_x psi'(x)^2 / 2,
+// psi' central differences of psi(rbar) (Eq. 8), kappa = -G/6 (the
+// P_b I + kappa grad psi grad psi form of the pressure tensor that Eq. (35)
+// modifies, with kappa fixed by the second-order expansion of Eq. 3).  One
+// block of 256 threads, fixed summation order.
+__global__ __launch_bounds__(256) void k_surface_tension(const double* __restrict__ rbar, RunDev d,
+                                                         double sigma, double* __restrict__ out) {
+  __shared__ double sm[256];
+  double acc = 0.0;
+  for (int x = threadIdx.x; x < d.nx; x += 256) {
+    const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+    const double d1 = 0.5 * (sqrt(psi2_of(rbar[xp], d)) - sqrt(psi2_of(rbar[xm], d)));
+    acc += d1 * d1;
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sm[threadIdx.x] += sm[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double G = -d.mG;
+    out[0] = (-G / 6.0 + 2.0 * G * G * sigma) * sm[0] * 0.5;
+  }
 }
 
 // Decode one stored population to FP64 exactly as the host decoder does:

@@ -134,7 +134,22 @@ RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64
   d.wBe3_2 = 3.0 / 36.0 * d.Be;
   d.rho_ref = rho_ref;
   d.run = run;
+  d.mrt = 0;
+  d.s_e = d.s_eps = d.s_q = d.inv_tau;
+  d.sig_e = d.sig_eps = d.sig;
   return d;
+}
+
+// Switch a lattice's constants to the MRT collision with energy, energy-square
+// and energy-flux rates r[0..2] (the density, momentum and stress moments relax
+// at 1/tau): sigma / (1/s - 1/2) of the improved scheme per moment.
+void set_mrt(RunDev& d, const lbm_params& p, const double* r) {
+  d.mrt = 1;
+  d.s_e = r[0];
+  d.s_eps = r[1];
+  d.s_q = r[2];
+  d.sig_e = p.sigma / (1.0 / r[0] - 0.5);
+  d.sig_eps = p.sigma / (1.0 / r[1] - 0.5);
 }
 
 // Encode FP64 populations f[a][y][x] into the pre-streamed storage buffer:
@@ -218,7 +233,7 @@ int resident_blocks(const void* fn, int threads) {
   return cache[fn] = ncu * occ;
 }
 
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT>
 hipError_t launch_step_t(const void* src, void* dst, const RunDev& d, int L,
                          const unsigned long long* base, unsigned long long local,
                          unsigned long long* flag, hipStream_t st) {
@@ -229,30 +244,30 @@ hipError_t launch_step_t(const void* src, void* dst, const RunDev& d, int L,
     grid = nstrips * ((d.ny + L - 1) / L);
   } else {  // balanced: resident capacity, at least 8 rows per block
     const int64_t rows = (int64_t)nstrips * d.ny;
-    grid = resident_blocks((const void*)k_step<S, NW, PF>, SW);
+    grid = resident_blocks((const void*)k_step<S, NW, PF, MRT>, SW);
     grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, rows / 8));
   }
   using E = typename Store<S>::E;
-  hipLaunchKernelGGL((k_step<S, NW, PF>), dim3(grid), dim3(SW), 0, st, static_cast<const E*>(src),
+  hipLaunchKernelGGL((k_step<S, NW, PF, MRT>), dim3(grid), dim3(SW), 0, st, static_cast<const E*>(src),
                      static_cast<E*>(dst), d, L, nstrips, base, local, flag);
   return hipGetLastError();
 }
 
-template <typename S>
+template <typename S, bool MRT = false>
 hipError_t launch_step_s(const Tile& t, const void* src, void* dst, const RunDev& d,
                          const unsigned long long* base, unsigned long long local,
                          unsigned long long* flag, hipStream_t st) {
   switch (t.nw * 10 + t.pf) {
-    case 11: return launch_step_t<S, 1, 1>(src, dst, d, t.L, base, local, flag, st);
-    case 12: return launch_step_t<S, 1, 2>(src, dst, d, t.L, base, local, flag, st);
-    case 21: return launch_step_t<S, 2, 1>(src, dst, d, t.L, base, local, flag, st);
-    case 22: return launch_step_t<S, 2, 2>(src, dst, d, t.L, base, local, flag, st);
-    case 41: return launch_step_t<S, 4, 1>(src, dst, d, t.L, base, local, flag, st);
-    case 42: return launch_step_t<S, 4, 2>(src, dst, d, t.L, base, local, flag, st);
-    case 81: return launch_step_t<S, 8, 1>(src, dst, d, t.L, base, local, flag, st);
-    case 82: return launch_step_t<S, 8, 2>(src, dst, d, t.L, base, local, flag, st);
-    case 161: return launch_step_t<S, 16, 1>(src, dst, d, t.L, base, local, flag, st);
-    default: return launch_step_t<S, 16, 2>(src, dst, d, t.L, base, local, flag, st);
+    case 11: return launch_step_t<S, 1, 1, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 12: return launch_step_t<S, 1, 2, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 21: return launch_step_t<S, 2, 1, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 22: return launch_step_t<S, 2, 2, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 41: return launch_step_t<S, 4, 1, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 42: return launch_step_t<S, 4, 2, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 81: return launch_step_t<S, 8, 1, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 82: return launch_step_t<S, 8, 2, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 161: return launch_step_t<S, 16, 1, MRT>(src, dst, d, t.L, base, local, flag, st);
+    default: return launch_step_t<S, 16, 2, MRT>(src, dst, d, t.L, base, local, flag, st);
   }
 }
 
@@ -300,6 +315,10 @@ hipError_t launch_step(int prec, const Tile& t, const void* src, void* dst, cons
     if (prec == LBM_PREC_F32DEV_F64)
       return launch_step2_s<f32s_f64a>(t, src, dst, d, base, local, flag, st);
     return launch_step2_s<__half>(t, src, dst, d, base, local, flag, st);
+  }
+  if (d.mrt) {  // one step per launch; FP64 or FP32 deviation storage (checked by lbm_set_mrt)
+    if (prec == LBM_PREC_F64) return launch_step_s<double, true>(t, src, dst, d, base, local, flag, st);
+    return launch_step_s<float, true>(t, src, dst, d, base, local, flag, st);
   }
   if (prec == LBM_PREC_F64) return launch_step_s<double>(t, src, dst, d, base, local, flag, st);
   if (prec == LBM_PREC_F32DEV) return launch_step_s<float>(t, src, dst, d, base, local, flag, st);
@@ -921,6 +940,7 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
 
 int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
   if (!c || !valid_tile(nw, L, depth, 16, steps)) return LBM_EINVAL;
+  if (c->d.mrt && steps != 1) return LBM_ENOTSUP;
   c->tile = Tile{nw, L, depth, steps};
   return prepare_graphs(c);
 }
@@ -950,7 +970,7 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, in
           cand.push_back(Tile{nw, L, pf, 1});
   }
   for (int nw : kStep2Waves) {
-    if (nw > 4 && 64 * (nw / 2) >= c->p.nx) continue;
+    if (c->d.mrt || (nw > 4 && 64 * (nw / 2) >= c->p.nx)) continue;
     for (int pf : {1, 2})
       for (int L : {0, 32, 64, 128})
         if (L <= 2 * c->p.ny) cand.push_back(Tile{nw, L, pf, 2});
@@ -972,7 +992,7 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, in
   c->tile = bt;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[{c->p.nx, c->p.ny, c->p.precision, 0}] = bt;
+    g_tune[{c->p.nx, c->p.ny, c->p.precision, c->d.mrt}] = bt;
   }
   const int gst = prepare_graphs(c);
   if (gst != LBM_OK) return gst;
@@ -988,6 +1008,25 @@ int lbm_set_graph_steps(lbm_ctx* c, int32_t k) {
   if (k > 0 && c->st == nullptr) return LBM_EINVAL;  // the null stream cannot be captured
   drop_graphs(c);
   c->graph_k = k;
+  return prepare_graphs(c);
+}
+
+int lbm_set_mrt(lbm_ctx* c, const double* rates) {
+  if (!c) return LBM_EINVAL;
+  if (!rates) {
+    const int mrt = c->d.mrt;
+    c->d = make_rundev(c->p, c->k, c->p.rho_ref, 0, 0);
+    if (mrt) drop_graphs(c);
+    return prepare_graphs(c);
+  }
+  if (c->p.scheme != LBM_SCHEME_IMPROVED) return LBM_ENOTSUP;
+  if (c->p.precision != LBM_PREC_F64 && c->p.precision != LBM_PREC_F32DEV) return LBM_ENOTSUP;
+  for (int i = 0; i < 3; ++i)
+    if (!(rates[i] > 0.0 && rates[i] < 2.0)) return LBM_EINVAL;
+  c->d = make_rundev(c->p, c->k, c->p.rho_ref, 0, 0);
+  set_mrt(c->d, c->p, rates);
+  if (c->tile.ts != 1) c->tile = Tile{c->tile.nw, c->tile.L, c->tile.pf, 1};
+  drop_graphs(c);  // the captured launches carry the old constants
   return prepare_graphs(c);
 }
 

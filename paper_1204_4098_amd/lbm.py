@@ -68,6 +68,7 @@ _SIGS = {
     "lbm_get_tile": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     "lbm_set_graph_steps": (C.c_int, [_vp, C.c_int32]),
     "lbm_graph_captures": (C.c_int, [_vp, _lp]),
+    "lbm_set_mrt": (C.c_int, [_vp, _vp]),
     "lbm_device_buffers": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), _ip]),
     "lbm_get_params": (C.c_int, [_vp, _P]),
     "lbm_destroy": (C.c_int, [_vp]),
@@ -271,6 +272,14 @@ class Lattice:
         n = C.c_int64()
         _check(lib().lbm_graph_captures(self.ctx, C.byref(n)), "lbm_graph_captures")
         return n.value
+
+    def set_mrt(self, rates=None):
+        """MRT collision with (s_e, s_eps, s_q); None restores BGK."""
+        if rates is None:
+            _check(lib().lbm_set_mrt(self.ctx, None), "lbm_set_mrt")
+            return
+        r = (C.c_double * 3)(*[float(v) for v in rates])
+        _check(lib().lbm_set_mrt(self.ctx, r), "lbm_set_mrt")
 
     def params(self) -> lbm_params:
         """The context's parameters (rho_ref resolved to the value in use)."""

@@ -174,13 +174,14 @@ def test_two_step_schemes_bitwise(L, scheme, eos, t):
     assert np.array_equal(outs[1], outs[0]) and np.array_equal(outs[2], outs[0])
 
 
+@pytest.mark.parametrize("depth", [1, 2])
 @pytest.mark.parametrize("shape", [(3, 3), (5, 4), (130, 7), (260, 5)])
-def test_two_step_edge_shapes(L, shape):
+def test_two_step_edge_shapes(L, shape, depth):
     nx, ny = shape
     gp, op = pair(L, nx, ny, t=0.9, tau=0.9, scheme=2, sigma=0.05)
     rng = np.random.default_rng(nx * 1000 + ny)
     rho0 = np.ascontiguousarray(0.1 + 0.02 * rng.random((ny, nx)))
-    errs, _, _ = _run_both(L, gp, op, rho0, [2, 25], tile=(4, 0, 2, 2))
+    errs, _, _ = _run_both(L, gp, op, rho0, [2, 25], tile=(4, 0, depth, 2))
     assert max(errs) < TOL64, errs
 
 

@@ -83,13 +83,13 @@ def test_two_step_deviation_storage_bitwise(L, prec):
     gp, _ = pair(L, 200, 60, t=0.8, tau=0.8, scheme=2, sigma=0.1, precision=prec)
     rho0 = slab_rho(200, 60, CS, 0.8, seed=12)
     outs = []
-    for tile in [(2, 8, 1), (4, 0, 2, 2), (8, 16, 1, 2)]:
+    for tile in [(2, 8, 1), (4, 0, 2, 2), (8, 16, 1, 2), (4, 32, 2, 2)]:
         lat = L.Lattice(gp, rho0)
         lat.set_tile(*tile)
         lat.step(31)
         outs.append(lat.save_state())
         lat.close()
-    assert outs[1] == outs[0] and outs[2] == outs[0]
+    assert all(o == outs[0] for o in outs[1:])
 
 
 def _batch_runs(L, prec=0):
@@ -111,7 +111,8 @@ def _batch_runs(L, prec=0):
     return gps, ops, rhos
 
 
-@pytest.mark.parametrize("tile", [(1, 16, 2), (2, 0, 1), (4, 8, 2), (8, 0, 2), (4, 0, 2, 2), (8, 32, 1, 2)])
+@pytest.mark.parametrize("tile", [(1, 16, 2), (2, 0, 1), (4, 8, 2), (8, 0, 2), (4, 0, 2, 2), (8, 32, 1, 2),
+                                  (4, 32, 2, 2)])
 def test_batch_equals_single_runs_bitwise(L, tile):
     gps, _, rhos = _batch_runs(L)
     b = L.Batch(gps, rhos)
