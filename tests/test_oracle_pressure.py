@@ -67,3 +67,47 @@ def test_other_schemes_are_rejected():
     p.scheme = lbm.SCHEME_EDM
     with pytest.raises(ValueError):
         pr.normal_pressure(p, np.full(8, 0.1))
+
+
+def test_surface_tension_of_a_uniform_state_is_zero_and_linear_in_sigma():
+    p = _params(0.8, 0.1, nx=8)
+    assert pr.surface_tension(p, np.full(8, 0.2)) == 0.0
+    _, rho = _equilibrium(0.8, 0.05, 1.0)
+    g = [pr.surface_tension(_params(0.8, s, nx=64), rho) for s in (0.0, 0.05, 0.1)]
+    # same profile: gamma is kappa(sigma) times one integral, kappa = 1/6 + 2 sigma at G = -1
+    assert abs((g[2] - g[0]) / (g[1] - g[0]) - 2.0) < 1e-12
+    assert abs(g[1] / g[0] - (1 / 6 + 0.1) / (1 / 6)) < 1e-12
+
+
+def _laplace_slope(t, sigma, radii=(10, 14, 20), n=56, steps=5000):
+    """Slope of the pressure jump p_in - p_out (p = p_EOS of the centre and corner
+    3x3 means) against 1/R (equimolar radius) over noise-free oracle droplets."""
+    Tc, _ = th.critical_cs()
+    c = th.maxwell_cs(t)
+    inv, dp = [], []
+    for r in radii:
+        p = lbm.Params(nx=n, ny=n, tau=1.0, scheme=lbm.SCHEME_IMPROVED, sigma=sigma, T=t * Tc)
+        f = lbm.init_equilibrium(synth.droplet(n, n, c.rho_l, c.rho_g, r, 2.0, 0.0, synth.BASE_SEED))
+        assert lbm.step(p, f, steps)[0] == lbm.OK
+        rho, _, _, pp = lbm.moments(p, f)
+        h = n // 2
+        rin, rout = rho[h, h], rho[0, 0]
+        inv.append(1.0 / np.sqrt((rho - rout).sum() / (np.pi * (rin - rout))))
+        dp.append(pp[h - 1:h + 2, h - 1:h + 2].mean() - pp[:3, :3].mean())
+    return np.polyfit(inv, dp, 1)[0]
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.1])
+def test_flat_surface_tension_matches_the_laplace_law(sigma):
+    # the mechanical gamma of a flat interface (kappa = -G/6 plus Eq. (35)'s 2 G^2 sigma)
+    # against the slope of Laplace's law over droplets, same temperature and sigma.
+    # Measured (0.85 Tc, radii 10-20): Laplace / flat = 0.948 (sigma 0) and 0.991 (0.1);
+    # sigma = 0.1 raises gamma 1.92x (flat) and 2.00x (Laplace).  A kappa of -G/4 or
+    # -G/12, or the sigma term dropped or doubled, moves the ratio by 30 % or more at
+    # one of the two sigmas.
+    t = 0.85
+    _, rho = _equilibrium(t, sigma, 1.0, steps=20000)
+    g_flat = pr.surface_tension(_params(t, sigma, nx=64), rho)
+    g_lap = _laplace_slope(t, sigma)
+    print(f"sigma {sigma}: flat {g_flat:.4e}, Laplace {g_lap:.4e}, ratio {g_lap / g_flat:.4f}")
+    assert abs(g_lap / g_flat - 1) < 0.08
