@@ -84,7 +84,12 @@ enum {
 /* Storage of populations: FP64, or deviations d_a = f_a - w_a rho_ref stored
  * in FP32 / FP16 with FP32 collision arithmetic (the EOS, psi and force stay
  * FP64), or FP32 deviations with FP64 collision arithmetic.  rho_ref = 0 stores
- * the populations themselves. */
+ * the populations themselves.  With FP32 storage and FP32 arithmetic, the mass
+ * of each node and its momentum change (exactly F) are restored in FP64 after
+ * the collision, so FP32 rounding is not a persistent mass or momentum source.
+ * Device layout of every precision: element (a, y, x) at (9 y + a) pitch + x,
+ * pitch = nx rounded up to a multiple of 64 (the nine direction rows of a
+ * lattice row are consecutive). */
 enum { LBM_PREC_F64 = 0, LBM_PREC_F32DEV = 1, LBM_PREC_F16DEV = 2, LBM_PREC_F32DEV_F64 = 3 };
 
 typedef struct {
@@ -154,6 +159,19 @@ int lbm_moments_device(lbm_ctx* c, double* rho, double* vx, double* vy, double* 
  * any other scheme returns LBM_ENOTSUP.  Uses the context's device scratch;
  * synchronous.  A column mean outside the range of Eq. (8) gives NaN there. */
 int lbm_flat_profile(lbm_ctx* c, double* rho_bar, double* p_n);
+
+/* Surface tension of the same flat interface (normal x), per interface of the
+ * periodic slab: gamma = integral of (P_n - P_t) across it.  After Eq. (35) the
+ * paper writes the pressure tensor as P_b delta_ij + kappa d_i psi d_j psi with
+ * the improved scheme adding 2 G^2 sigma to kappa, so P_n - P_t = (kappa +
+ * 2 G^2 sigma) psi'^2; kappa is not given there, and is taken as -G/6, the only
+ * value for which a tensor of that form has the second-order expansion of
+ * Eq. (3) on this stencil as its divergence.  gamma = (-G/6 + 2 G^2 sigma)
+ * sum_x psi'(x)^2 / 2 over the column-mean profile, psi' as in
+ * lbm_flat_profile.  The improved scheme only (LBM_ENOTSUP otherwise; with
+ * the MRT collision the stress moments relax at 1/tau, so the same gamma
+ * holds, while p_n of lbm_flat_profile is not supported there).  Synchronous. */
+int lbm_surface_tension(lbm_ctx* c, double* gamma);
 
 /* Total mass: fixed[0..1] = the 128-bit integer sum over nodes of
  * round-to-nearest-even(rho * 2^40) as (low, high) 64-bit words, with

@@ -41,7 +41,8 @@ constexpr int LMAX = 128;  // largest chunk height (rows) k_step marches (halo a
 // Per-lattice constants, prepared on the host.
 struct RunDev {
   int32_t nx, ny, pitch, eos;
-  int64_t plane;            // elements per direction plane (ny * pitch)
+  int64_t plane;            // elements between direction a and a+1 at one node
+  int64_t rs;               // elements between row y and y+1 of one direction
   int64_t off;              // element offset of this lattice in the population pool
   double RT, c1, c2;        // EOS constants (see EosConst)
   double two_over_G, mG;    // 2/G and -G
@@ -75,9 +76,12 @@ struct Item {
 // show no difference.
 struct f32s_f64a {};  // FP32 deviation storage with FP64 collision arithmetic
 template <typename S> struct Store;
+// kConserve: after the FP32 collision, restore the node's mass and momentum
+// change exactly (see conserve()).
 template <> struct Store<double> {
   using E = double;
   using R = double;
+  static constexpr bool kConserve = false;
   static __device__ __forceinline__ R ld(const E* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(v, p); }
   static __device__ __forceinline__ R round(R v) { return v; }
@@ -85,6 +89,7 @@ template <> struct Store<double> {
 template <> struct Store<float> {
   using E = float;
   using R = float;
+  static constexpr bool kConserve = true;
   static __device__ __forceinline__ R ld(const E* p) { return *p; }
   static __device__ __forceinline__ void st(E* p, R v) { *p = v; }
   static __device__ __forceinline__ R round(R v) { return v; }
@@ -92,6 +97,7 @@ template <> struct Store<float> {
 template <> struct Store<f32s_f64a> {
   using E = float;
   using R = double;
+  static constexpr bool kConserve = false;
   static __device__ __forceinline__ R ld(const E* p) { return double(__builtin_nontemporal_load(p)); }
   static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(float(v), p); }
   static __device__ __forceinline__ R round(R v) { return double(float(v)); }
@@ -99,6 +105,7 @@ template <> struct Store<f32s_f64a> {
 template <> struct Store<__half> {
   using E = __half;
   using R = float;
+  static constexpr bool kConserve = false;
   static __device__ __forceinline__ R ld(const E* p) { return __half2float(*p); }
   static __device__ __forceinline__ void st(E* p, R v) { *p = __float2half_rn(v); }
   static __device__ __forceinline__ R round(R v) { return __half2float(__float2half_rn(v)); }
@@ -138,9 +145,9 @@ __device__ __forceinline__ void pull9(const typename Store<S>::E* __restrict__ s
   const int yp = y == d.ny - 1 ? 0 : y + 1;
   const int64_t P = d.plane;
   using T = Store<S>;
-  const typename T::E* r0 = src + (int64_t)y * d.pitch;
-  const typename T::E* rm = src + (int64_t)ym * d.pitch;
-  const typename T::E* rp = src + (int64_t)yp * d.pitch;
+  const typename T::E* r0 = src + (int64_t)y * d.rs;
+  const typename T::E* rm = src + (int64_t)ym * d.rs;
+  const typename T::E* rp = src + (int64_t)yp * d.rs;
   f[0] = T::ld(r0 + c.x);
   f[1] = T::ld(r0 + P + c.xm);
   f[2] = T::ld(rm + 2 * P + c.x);
@@ -343,6 +350,61 @@ __device__ __forceinline__ R mom_y(const R (&s)[9]) {
   return ((s[2] - s[4]) + (s[5] - s[7])) + (s[6] - s[8]);
 }
 
+// Mass and momentum of nine FP32 values summed in FP64 (exact unless the
+// values span more than 29 binary orders of magnitude, and then wrong only by
+// an FP64 rounding of the largest, far below an FP32 rounding).
+__device__ __forceinline__ void exact_moments(const float (&s)[9], double& m, double& jx, double& jy) {
+#pragma clang fp contract(off)
+  double t[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) t[a] = double(s[a]);
+  m = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7])) + t[8];
+  jx = ((t[1] - t[3]) + (t[5] - t[7])) + (t[8] - t[6]);
+  jy = ((t[2] - t[4]) + (t[5] - t[7])) + (t[6] - t[8]);
+}
+
+// The collision conserves mass and changes the momentum by exactly F (every
+// forcing scheme here, BGK or MRT).  In FP32 arithmetic each updated
+// population carries its own rounding, and at a steady state the same
+// roundings recur every step: a persistent mass and momentum source at every
+// node that the slow bulk dynamics integrate into visibly shifted coexistence
+// densities.  conserve() puts the momentum change of the new populations back
+// to exactly F (half the x defect on e1 and -e1, likewise y on e2, -e4) and the
+// mass back to exactly the old mass on the rest population, computed in FP64;
+// what remains is one FP32 rounding of five values.
+__device__ __forceinline__ void conserve(float (&s)[9], double m_t, double jx_t, double jy_t) {
+#pragma clang fp contract(off)
+  double jx, jy, m;
+  exact_moments(s, m, jx, jy);
+  const double dx = 0.5 * (jx_t - jx), dy = 0.5 * (jy_t - jy);
+  s[1] = float(double(s[1]) + dx);
+  s[3] = float(double(s[3]) - dx);
+  s[2] = float(double(s[2]) + dy);
+  s[4] = float(double(s[4]) - dy);
+  double t[9];
+#pragma unroll
+  for (int a = 1; a < 9; ++a) t[a] = double(s[a]);
+  const double rest = ((t[1] + t[2]) + (t[3] + t[4])) + ((t[5] + t[6]) + (t[7] + t[8]));
+  s[0] = float(m_t - rest);
+}
+
+// One node update: collision (BGK or MRT) of the pulled values s with the
+// force (Fx, Fy) (FP64), then, for FP32 storage, conserve().
+template <typename S, bool MRT>
+__device__ __forceinline__ void update_node(typename Store<S>::R (&s)[9],
+                                            typename Store<S>::R drho, double rho64, double Fx,
+                                            double Fy, typename Store<S>::R ip2, const RunDev& d) {
+  using R = typename Store<S>::R;
+  if constexpr (Store<S>::kConserve) {
+    double m0, jx0, jy0;
+    exact_moments(s, m0, jx0, jy0);
+    collide_any<MRT, R>(s, drho, R(rho64), mom_x(s), mom_y(s), R(Fx), R(Fy), ip2, d);
+    conserve(s, m0, jx0 + Fx, jy0 + Fy);
+  } else {
+    collide_any<MRT, R>(s, drho, R(rho64), mom_x(s), mom_y(s), R(Fx), R(Fy), ip2, d);
+  }
+}
+
 // One tile: columns [x0, x0+ncols), rows [y0, y0+nrows), nrows <= LMAX.
 // All threads of the block call it (barriers inside); ring is [4][SW+2],
 // haloL/haloR [LMAX+2].  PF is the number of rows whose loads are in flight
@@ -426,8 +488,8 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
       const double rho64 = rref + double(drho);
       bad |= !(psi2c > 0.0) || !(rho64 > 0.0);
       const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
-      collide_any<MRT, R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
-      typename T::E* row = dst + (int64_t)y * d.pitch;
+      update_node<S, MRT>(fc, drho, rho64, Fx, Fy, ip2, d);
+      typename T::E* row = dst + (int64_t)y * d.rs;
 #pragma unroll
       for (int a = 0; a < 9; ++a) T::st(row + a * d.plane + cx.x, fc[a]);
 #pragma unroll
@@ -454,7 +516,7 @@ __device__ __forceinline__ void copy_tile(const typename Store<S>::E* __restrict
   if ((int)threadIdx.x >= ncols) return;
   const int x = x0 + (int)threadIdx.x;
   for (int j = 0; j < nrows; ++j) {
-    const int64_t o = (int64_t)(y0 + j) * d.pitch + x;
+    const int64_t o = (int64_t)(y0 + j) * d.rs + x;
 #pragma unroll
     for (int a = 0; a < 9; ++a) dst[o + a * d.plane] = src[o + a * d.plane];
   }
@@ -657,7 +719,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
         const bool chk = out && y1 >= y0 && y1 < y0 + nrows;
         bad1 |= chk && (!(psi2c > 0.0) || !(rho64 > 0.0));
         const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
-        collide<R>(fc, drho, R(rho64), mom_x(fc), mom_y(fc), R(Fx), R(Fy), ip2, d);
+        update_node<S, false>(fc, drho, rho64, Fx, Fy, ip2, d);
 #pragma unroll
         for (int a = 0; a < 9; ++a) gA[a] = T::round(fc[a]);
       }
@@ -680,9 +742,9 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
       const double rho64 = rref + double(drho);
       bad2 |= out && (!(psi2p > 0.0) || !(rho64 > 0.0));
       const R ip2 = d.sig != 0.0 ? rcp(R(psi2p)) : R(0);
-      collide<R>(hp, drho, R(rho64), mom_x(hp), mom_y(hp), R(Fx), R(Fy), ip2, d);
+      update_node<S, false>(hp, drho, rho64, Fx, Fy, ip2, d);
       if (out) {
-        typename T::E* orow = dst + (int64_t)wrapy(r) * d.pitch;
+        typename T::E* orow = dst + (int64_t)wrapy(r) * d.rs;
 #pragma unroll
         for (int a = 0; a < 9; ++a) T::st(orow + a * d.plane + cx.x, hp[a]);
       }
@@ -1034,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_mass(const typename Store<S>::E* __rest
     const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
     const int64_t P = d.plane;
-    const int64_t r0 = (int64_t)y * d.pitch, rm = (int64_t)ym * d.pitch, rp = (int64_t)yp * d.pitch;
+    const int64_t r0 = (int64_t)y * d.rs, rm = (int64_t)ym * d.rs, rp = (int64_t)yp * d.rs;
     const int64_t idx[9] = {r0 + x,          P + r0 + xm,     2 * P + rm + x,
                             3 * P + r0 + xp, 4 * P + rp + x,  5 * P + rm + xm,
                             6 * P + rm + xp, 7 * P + rp + xp, 8 * P + rp + xm};

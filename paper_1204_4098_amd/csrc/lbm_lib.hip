@@ -45,15 +45,17 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int esize_of(int prec) { return prec == LBM_PREC_F64 ? 8 : prec == LBM_PREC_F16DEV ? 2 : 4; }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
-#ifndef LBM_PLANE_PAD_BYTES
-#define LBM_PLANE_PAD_BYTES 0
-#endif
-// Elements between consecutive direction planes: ny rows of pitch elements,
-// plus an optional pad that moves the nine planes off a common power-of-two
-// stride (so concurrent streams do not fall on the same memory channels).
-int64_t plane_of(int nx, int ny, int esize) {
-  return (int64_t)pitch_of(nx) * ny + LBM_PLANE_PAD_BYTES / esize;
-}
+// Population storage, row-interleaved: element (a, y, x) at a * plane + y * rs
+// + x with rows of pitch elements (nx rounded up to 64), plane = pitch and rs =
+// 9 pitch, so the nine direction rows of one lattice row are consecutive in
+// memory.  A row of the march then reads and writes three 9-row blocks close
+// together instead of 18 rows in nine planes far apart: on the 4096 x 4096
+// FP64 workload the two-step kernel runs 491 us per launch against 525 us with
+// plane-major storage (plane = ny pitch, rs = pitch), and a memory-only
+// marching probe reaches 5.5 against 5.2 TB/s.
+int64_t plane_of(int nx) { return (int64_t)pitch_of(nx); }
+int64_t rs_of(int nx) { return 9 * (int64_t)pitch_of(nx); }
+int64_t elems_of(int nx, int ny) { return 9 * (int64_t)pitch_of(nx) * ny; }
 
 int validate(const lbm_params& p) {
   if (p.nx < 3 || p.ny < 3) return LBM_EINVAL;
@@ -86,7 +88,8 @@ RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64
   d.ny = p.ny;
   d.pitch = pitch_of(p.nx);
   d.eos = p.eos;
-  d.plane = plane_of(p.nx, p.ny, esize_of(p.precision));
+  d.plane = plane_of(p.nx);
+  d.rs = rs_of(p.nx);
   d.off = off;
   d.RT = k.RT;
   d.c1 = k.c1;
@@ -157,9 +160,8 @@ void set_mrt(RunDev& d, const lbm_params& p, const double* r) {
 // (x + e_a, y + e_a); so buf[a][y][x] = f[a][y + ey][x + ex] (periodic).
 template <typename S>
 void encode_buffer(const lbm_params& p, double rref, const double* f, std::vector<char>& out) {
-  const int pitch = pitch_of(p.nx);
-  const size_t plane = plane_of(p.nx, p.ny, sizeof(S)), n = (size_t)p.nx * p.ny;
-  out.assign(9 * plane * sizeof(S), 0);
+  const size_t plane = plane_of(p.nx), rs = rs_of(p.nx), n = (size_t)p.nx * p.ny;
+  out.assign(elems_of(p.nx, p.ny) * sizeof(S), 0);
   S* b = reinterpret_cast<S*>(out.data());
   for (int a = 0; a < 9; ++a)
     for (int y = 0; y < p.ny; ++y) {
@@ -168,26 +170,25 @@ void encode_buffer(const lbm_params& p, double rref, const double* f, std::vecto
         const int xs = (x + kEXh[a] + p.nx) % p.nx;
         const double v = f[a * n + (size_t)ys * p.nx + xs];
         if constexpr (std::is_same<S, double>::value)
-          b[a * plane + (size_t)y * pitch + x] = v;
+          b[a * plane + (size_t)y * rs + x] = v;
         else if constexpr (std::is_same<S, float>::value)
-          b[a * plane + (size_t)y * pitch + x] = (float)(v - kWh[a] * rref);
+          b[a * plane + (size_t)y * rs + x] = (float)(v - kWh[a] * rref);
         else  // RNE to FP32, then RNE to FP16
-          b[a * plane + (size_t)y * pitch + x] = __float2half_rn((float)(v - kWh[a] * rref));
+          b[a * plane + (size_t)y * rs + x] = __float2half_rn((float)(v - kWh[a] * rref));
       }
     }
 }
 
 template <typename S>
 void decode_buffer(const lbm_params& p, double rref, const char* raw, double* f) {
-  const int pitch = pitch_of(p.nx);
-  const size_t plane = plane_of(p.nx, p.ny, sizeof(S)), n = (size_t)p.nx * p.ny;
+  const size_t plane = plane_of(p.nx), rs = rs_of(p.nx), n = (size_t)p.nx * p.ny;
   const S* b = reinterpret_cast<const S*>(raw);
   for (int a = 0; a < 9; ++a)
     for (int y = 0; y < p.ny; ++y) {
       const int ys = (y - kEYh[a] + p.ny) % p.ny;
       for (int x = 0; x < p.nx; ++x) {
         const int xs = (x - kEXh[a] + p.nx) % p.nx;
-        const S v = b[a * plane + (size_t)ys * pitch + xs];
+        const S v = b[a * plane + (size_t)ys * rs + xs];
         double d;
         if constexpr (std::is_same<S, double>::value) {
           d = v;
@@ -543,7 +544,7 @@ namespace {
 
 size_t raw_bytes_of(const lbm_params& p) {
   const int es = esize_of(p.precision);
-  return 9 * (size_t)plane_of(p.nx, p.ny, es) * es;
+  return (size_t)elems_of(p.nx, p.ny) * es;
 }
 
 size_t ctx_layout(const lbm_params& p, size_t* pop, size_t* aux, size_t* parts, size_t* misc) {
@@ -816,7 +817,7 @@ int lbm_moments(lbm_ctx* c, double* rho, double* vx, double* vy, double* p) {
 
 int lbm_flat_profile(lbm_ctx* c, double* rho_bar, double* p_n) {
   if (!c || !rho_bar) return LBM_EINVAL;
-  if (p_n && c->p.scheme != LBM_SCHEME_IMPROVED) return LBM_ENOTSUP;
+  if (p_n && (c->p.scheme != LBM_SCHEME_IMPROVED || c->d.mrt)) return LBM_ENOTSUP;
   const size_t n = (size_t)c->p.nx * c->p.ny;
   double* a = c->aux;
   // rho plane at a; the column means and the pressure reuse the velocity plane
@@ -844,6 +845,25 @@ static void mass_words(const unsigned long long w[3], int64_t* fixed, double* ma
   if (mass) std::memcpy(mass, &w[2], sizeof(double));
 }
 
+int lbm_surface_tension(lbm_ctx* c, double* gamma) {
+  if (!c || !gamma) return LBM_EINVAL;
+  if (c->p.scheme != LBM_SCHEME_IMPROVED) return LBM_ENOTSUP;
+  const size_t n = (size_t)c->p.nx * c->p.ny;
+  double* a = c->aux;
+  double* rb = a + n;  // column means and the result reuse the velocity plane
+  double* g = rb + c->p.nx;
+  HIPCHK(launch_moments(c->p.precision, c->buf[c->cur], c->d, a, a + n, a + 2 * n, a + 3 * n,
+                        a + 4 * n, c->st));
+  hipLaunchKernelGGL(k_colmean, dim3((c->p.nx + 255) / 256), dim3(256), 0, c->st, (const double*)a,
+                     c->p.nx, c->p.ny, rb);
+  hipLaunchKernelGGL(k_surface_tension, dim3(1), dim3(256), 0, c->st, (const double*)rb, c->d,
+                     c->p.sigma, g);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(gamma, g, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return lbm_status(c, nullptr, nullptr);
+}
+
 int lbm_mass(lbm_ctx* c, int64_t* fixed, double* mass) {
   if (!c) return LBM_EINVAL;
   HIPCHK(launch_mass(c->p.precision, c->buf[c->cur], c->d, c->part_i, c->part_d, c->mass_out, c->st));
@@ -866,7 +886,8 @@ int lbm_mass_noalloc(const void* dev_populations, int32_t nx, int32_t ny, int32_
   d.nx = nx;
   d.ny = ny;
   d.pitch = pitch_of(nx);
-  d.plane = plane_of(nx, ny, esize_of(precision));
+  d.plane = plane_of(nx);
+  d.rs = rs_of(nx);
   d.rho_ref = precision == LBM_PREC_F64 ? 0.0 : rho_ref;
   __int128* pi = reinterpret_cast<__int128*>(base);
   double* pd = reinterpret_cast<double*>(pi + kMassBlocks);
@@ -917,7 +938,7 @@ int lbm_state_bytes(lbm_ctx* c, size_t* bytes) {
 
 int lbm_save_state(lbm_ctx* c, void* host, size_t bytes) {
   if (!c || !host || bytes < sizeof(CkptHeader) + c->raw_bytes) return LBM_EINVAL;
-  CkptHeader h{kCkptMagic, 1, c->step, c->p.precision, c->p.nx, c->p.ny, 0, c->p.rho_ref, c->raw_bytes};
+  CkptHeader h{kCkptMagic, 2, c->step, c->p.precision, c->p.nx, c->p.ny, 0, c->p.rho_ref, c->raw_bytes};
   std::memcpy(host, &h, sizeof h);
   HIPCHK(hipMemcpyAsync(static_cast<char*>(host) + sizeof h, c->buf[c->cur], c->raw_bytes,
                         hipMemcpyDeviceToHost, c->st));
@@ -929,7 +950,7 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
   if (!c || !host || bytes < sizeof(CkptHeader)) return LBM_EINVAL;
   CkptHeader h;
   std::memcpy(&h, host, sizeof h);
-  if (h.magic != kCkptMagic || h.version != 1 || h.precision != c->p.precision || h.nx != c->p.nx ||
+  if (h.magic != kCkptMagic || h.version != 2 || h.precision != c->p.precision || h.nx != c->p.nx ||
       h.ny != c->p.ny || h.raw_bytes != c->raw_bytes || bytes < sizeof h + c->raw_bytes ||
       !(h.rho_ref == c->p.rho_ref) || h.step < 0)
     return LBM_EINVAL;
@@ -1101,7 +1122,7 @@ struct BatchLayout {
 };
 
 int64_t run_elems(const lbm_params& q) {
-  return (9 * plane_of(q.nx, q.ny, esize_of(q.precision)) + 63) / 64 * 64;
+  return (elems_of(q.nx, q.ny) + 63) / 64 * 64;
 }
 
 BatchLayout batch_layout(int n, const lbm_params* p) {

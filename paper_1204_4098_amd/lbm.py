@@ -58,6 +58,7 @@ _SIGS = {
     "lbm_mass": (C.c_int, [_vp, _lp, _dp]),
     "lbm_mass_noalloc": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, _vp, _lp, _dp]),
     "lbm_flat_profile": (C.c_int, [_vp, _vp, _vp]),
+    "lbm_surface_tension": (C.c_int, [_vp, _dp]),
     "lbm_get_populations": (C.c_int, [_vp, _vp, _lp]),
     "lbm_set_populations": (C.c_int, [_vp, _vp, C.c_int64]),
     "lbm_state_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
@@ -214,6 +215,12 @@ class Lattice:
         _check(lib().lbm_flat_profile(self.ctx, rb.ctypes.data, None if pn is None else pn.ctypes.data),
                "lbm_flat_profile")
         return rb, pn
+
+    def surface_tension(self) -> float:
+        """gamma of a flat interface with normal x (improved scheme; see lbm.h)."""
+        g = C.c_double()
+        _check(lib().lbm_surface_tension(self.ctx, C.byref(g)), "lbm_surface_tension")
+        return g.value
 
     def moments_device(self):
         out = [torch.empty((self.p.ny, self.p.nx), dtype=torch.float64, device=self.device) for _ in range(4)]
