@@ -290,8 +290,10 @@ int lbm_batch_coexistence(lbm_batch* b, double* rho_l, double* rho_g, int32_t* s
  * has diverged. */
 int lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* vx, double* vy, double* p);
 int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f);
-/* Tiles of the batch work list (rows = 0: one item per strip of up to 128
- * rows; rows otherwise >= 4), tuned over the whole batch like lbm_tune;
+/* Tiles of the batch work list (rows >= 4: items of that many rows, spread
+ * over the grid; rows = 0: the balanced schedule, in which the rows of all
+ * whole-run strips, concatenated, are split evenly over a grid sized to the
+ * resident capacity), tuned over the whole batch like lbm_tune;
  * waves in {1, 2, 4, 8}; steps = 2 (waves 4 or 8) runs two time steps per
  * launch as for a single lattice, with strips of at most 64*waves - 6
  * columns. */

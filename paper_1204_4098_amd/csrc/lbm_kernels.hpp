@@ -62,10 +62,40 @@ struct RunDev {
   double s_e, s_eps, s_q, sig_e, sig_eps;
 };
 
-// A tile of the batched launch.
+// A tile of the batched launch.  In the balanced schedule an item is a whole
+// strip of one run and row0 is its first row in the concatenated row space of
+// all items (rows of earlier items summed); item lists leave it 0.
 struct Item {
-  int32_t run, x0, y0, ncols, nrows, pad;
+  int32_t run, x0, y0, ncols, nrows, row0;
 };
+
+// Balanced schedule of a batch: the concatenated rows of all strips, [0,
+// total), are split evenly over the grid; block t (XCD-remapped) marches its
+// share, one piece per item it overlaps (at most `cap` rows per piece), and
+// calls piece(item, first row in the item, rows).
+template <class Piece>
+__device__ __forceinline__ void balanced_pieces(const Item* __restrict__ items, int nitems, int total,
+                                                int t, int cap, Piece&& piece) {
+  int64_t r = (int64_t)total * t / gridDim.x;
+  const int64_t e = (int64_t)total * (t + 1) / gridDim.x;
+  if (r >= e) return;
+  int lo = 0, hi = nitems - 1;  // last item whose row0 <= r
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].row0 <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  int i = lo;
+  while (r < e) {
+    const Item it = items[i];
+    const int y = (int)(r - it.row0);
+    const int n = (int)min(min(e - r, (int64_t)(it.nrows - y)), (int64_t)cap);
+    piece(it, y, n);
+    r += n;
+    if (y + n >= it.nrows) ++i;
+    __syncthreads();  // LDS is reused by the next piece
+  }
+}
 
 // Storage traits: E = element type in memory, R = collision arithmetic type;
 // round(v) = the value a store followed by a load would give.  Cache policy
@@ -875,14 +905,27 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step(const typename Store<S>:
                                                         typename Store<S>::E* __restrict__ dst,
                                                         const RunDev* __restrict__ runs,
                                                         const Item* __restrict__ items, int nitems,
+                                                        int total,
                                                         const unsigned long long* stepbase,
                                                         unsigned long long steplocal,
                                                         unsigned long long* flags) {
   __shared__ double ring[4][64 * NW + 2];
   __shared__ double haloL[LMAX + 2], haloR[LMAX + 2];
+  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
+  if (total > 0) {  // balanced schedule over whole-strip items
+    balanced_pieces(items, nitems, total, xcd_remap(blockIdx.x, gridDim.x), LMAX,
+                    [&](const Item& it, int y, int n) {
+                      const RunDev d = runs[it.run];
+                      if (flags[it.run] < step)
+                        copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0 + y, it.ncols, n);
+                      else
+                        tile_step<S, NW, PF, MRT>(src + d.off, dst + d.off, d, it.x0, it.y0 + y, it.ncols,
+                                                  n, step, &flags[it.run], ring, haloL, haloR);
+                    });
+    return;
+  }
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, nb = gridDim.x >> 3;
   const int lo = (int)((int64_t)nitems * xcd / 8), hi = (int)((int64_t)nitems * (xcd + 1) / 8);
-  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
   for (int i = lo + slot; i < hi; i += nb) {
     const Item it = items[i];
     const RunDev d = runs[it.run];
@@ -903,6 +946,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>
                                                          typename Store<S>::E* __restrict__ dst,
                                                          const RunDev* __restrict__ runs,
                                                          const Item* __restrict__ items, int nitems,
+                                                         int total,
                                                          const unsigned long long* stepbase,
                                                          unsigned long long steplocal,
                                                          unsigned long long* flags) {
@@ -910,9 +954,21 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>
   __shared__ double ring1[4][64 * NW];
   __shared__ double ring2[4][64 * NW];
   __shared__ R xch[6][64 * NW];
+  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
+  if (total > 0) {  // balanced schedule over whole-strip items (no row cap: no per-row arrays)
+    balanced_pieces(items, nitems, total, xcd_remap(blockIdx.x, gridDim.x), 1 << 30,
+                    [&](const Item& it, int y, int n) {
+                      const RunDev d = runs[it.run];
+                      if (flags[it.run] < step)
+                        copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0 + y, it.ncols, n);
+                      else
+                        tile_step2<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0 + y, it.ncols, n,
+                                              step, &flags[it.run], ring1, ring2, xch);
+                    });
+    return;
+  }
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, nb = gridDim.x >> 3;
   const int lo = (int)((int64_t)nitems * xcd / 8), hi = (int)((int64_t)nitems * (xcd + 1) / 8);
-  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
   for (int i = lo + slot; i < hi; i += nb) {
     const Item it = items[i];
     const RunDev d = runs[it.run];

@@ -327,82 +327,88 @@ hipError_t launch_step(int prec, const Tile& t, const void* src, void* dst, cons
   return launch_step_s<__half>(t, src, dst, d, base, local, flag, st);
 }
 
+// Grid of a batch launch: item lists take at most one block per item (a
+// multiple of 8, one eighth of the list per XCD); the balanced schedule
+// (total > 0 rows) the resident capacity, at least 8 rows per block.
+int batch_grid(const void* fn, int threads, int nitems, int total) {
+  int g = resident_blocks(fn, threads);
+  if (total > 0) return (int)std::max<int64_t>(1, std::min<int64_t>(g, total / 8));
+  g = std::min(g, (nitems + 7) / 8 * 8);
+  return std::max(8, g / 8 * 8);
+}
+
 template <typename S, int NW, int PF>
 hipError_t launch_batch_t(const void* src, void* dst, const RunDev* runs, const Item* items,
-                          int nitems, const unsigned long long* base, unsigned long long local,
-                          unsigned long long* flags, hipStream_t st) {
-  int g = resident_blocks((const void*)k_batch_step<S, NW, PF>, 64 * NW);
-  g = std::min(g, (nitems + 7) / 8 * 8);
-  g = std::max(8, g / 8 * 8);
+                          int nitems, int total, const unsigned long long* base,
+                          unsigned long long local, unsigned long long* flags, hipStream_t st) {
+  const int g = batch_grid((const void*)k_batch_step<S, NW, PF>, 64 * NW, nitems, total);
   using E = typename Store<S>::E;
   hipLaunchKernelGGL((k_batch_step<S, NW, PF>), dim3(g), dim3(64 * NW), 0, st,
-                     static_cast<const E*>(src), static_cast<E*>(dst), runs, items, nitems, base,
-                     local, flags);
+                     static_cast<const E*>(src), static_cast<E*>(dst), runs, items, nitems, total,
+                     base, local, flags);
   return hipGetLastError();
 }
 
 template <typename S>
 hipError_t launch_batch_s(const Tile& t, const void* src, void* dst, const RunDev* runs,
-                          const Item* items, int nitems, const unsigned long long* base,
+                          const Item* items, int nitems, int total, const unsigned long long* base,
                           unsigned long long local, unsigned long long* flags, hipStream_t st) {
   switch (t.nw * 10 + t.pf) {
-    case 11: return launch_batch_t<S, 1, 1>(src, dst, runs, items, nitems, base, local, flags, st);
-    case 12: return launch_batch_t<S, 1, 2>(src, dst, runs, items, nitems, base, local, flags, st);
-    case 21: return launch_batch_t<S, 2, 1>(src, dst, runs, items, nitems, base, local, flags, st);
-    case 22: return launch_batch_t<S, 2, 2>(src, dst, runs, items, nitems, base, local, flags, st);
-    case 41: return launch_batch_t<S, 4, 1>(src, dst, runs, items, nitems, base, local, flags, st);
-    case 42: return launch_batch_t<S, 4, 2>(src, dst, runs, items, nitems, base, local, flags, st);
-    case 81: return launch_batch_t<S, 8, 1>(src, dst, runs, items, nitems, base, local, flags, st);
-    default: return launch_batch_t<S, 8, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 11: return launch_batch_t<S, 1, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 12: return launch_batch_t<S, 1, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 21: return launch_batch_t<S, 2, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 22: return launch_batch_t<S, 2, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 41: return launch_batch_t<S, 4, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 42: return launch_batch_t<S, 4, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 81: return launch_batch_t<S, 8, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    default: return launch_batch_t<S, 8, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
   }
 }
 
 template <typename S, int NW, int PF>
 hipError_t launch_batch2_t(const void* src, void* dst, const RunDev* runs, const Item* items,
-                           int nitems, const unsigned long long* base, unsigned long long local,
-                           unsigned long long* flags, hipStream_t st) {
-  int g = resident_blocks((const void*)k_batch_step2<S, NW, PF>, 64 * NW);
-  g = std::min(g, (nitems + 7) / 8 * 8);
-  g = std::max(8, g / 8 * 8);
+                           int nitems, int total, const unsigned long long* base,
+                           unsigned long long local, unsigned long long* flags, hipStream_t st) {
+  const int g = batch_grid((const void*)k_batch_step2<S, NW, PF>, 64 * NW, nitems, total);
   using E = typename Store<S>::E;
   hipLaunchKernelGGL((k_batch_step2<S, NW, PF>), dim3(g), dim3(64 * NW), 0, st,
-                     static_cast<const E*>(src), static_cast<E*>(dst), runs, items, nitems, base,
-                     local, flags);
+                     static_cast<const E*>(src), static_cast<E*>(dst), runs, items, nitems, total,
+                     base, local, flags);
   return hipGetLastError();
 }
 
 template <typename S>
 hipError_t launch_batch2_s(const Tile& t, const void* src, void* dst, const RunDev* runs,
-                           const Item* items, int nitems, const unsigned long long* base,
+                           const Item* items, int nitems, int total, const unsigned long long* base,
                            unsigned long long local, unsigned long long* flags, hipStream_t st) {
   switch (t.nw * 10 + t.pf) {
-    case 41: return launch_batch2_t<S, 4, 1>(src, dst, runs, items, nitems, base, local, flags, st);
-    case 42: return launch_batch2_t<S, 4, 2>(src, dst, runs, items, nitems, base, local, flags, st);
-    case 81: return launch_batch2_t<S, 8, 1>(src, dst, runs, items, nitems, base, local, flags, st);
-    default: return launch_batch2_t<S, 8, 2>(src, dst, runs, items, nitems, base, local, flags, st);
+    case 41: return launch_batch2_t<S, 4, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 42: return launch_batch2_t<S, 4, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 81: return launch_batch2_t<S, 8, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    default: return launch_batch2_t<S, 8, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
   }
 }
 
 // One launch of the batch tile: t.ts time steps (1 or 2) of every active run.
 hipError_t launch_batch(int prec, const Tile& t, const void* src, void* dst, const RunDev* runs,
-                        const Item* items, int nitems, const unsigned long long* base,
+                        const Item* items, int nitems, int total, const unsigned long long* base,
                         unsigned long long local, unsigned long long* flags, hipStream_t st) {
   if (t.ts == 2) {
     if (prec == LBM_PREC_F64)
-      return launch_batch2_s<double>(t, src, dst, runs, items, nitems, base, local, flags, st);
+      return launch_batch2_s<double>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
     if (prec == LBM_PREC_F32DEV)
-      return launch_batch2_s<float>(t, src, dst, runs, items, nitems, base, local, flags, st);
+      return launch_batch2_s<float>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
     if (prec == LBM_PREC_F32DEV_F64)
-      return launch_batch2_s<f32s_f64a>(t, src, dst, runs, items, nitems, base, local, flags, st);
-    return launch_batch2_s<__half>(t, src, dst, runs, items, nitems, base, local, flags, st);
+      return launch_batch2_s<f32s_f64a>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
+    return launch_batch2_s<__half>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
   }
   if (prec == LBM_PREC_F64)
-    return launch_batch_s<double>(t, src, dst, runs, items, nitems, base, local, flags, st);
+    return launch_batch_s<double>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
   if (prec == LBM_PREC_F32DEV)
-    return launch_batch_s<float>(t, src, dst, runs, items, nitems, base, local, flags, st);
+    return launch_batch_s<float>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
   if (prec == LBM_PREC_F32DEV_F64)
-    return launch_batch_s<f32s_f64a>(t, src, dst, runs, items, nitems, base, local, flags, st);
-  return launch_batch_s<__half>(t, src, dst, runs, items, nitems, base, local, flags, st);
+    return launch_batch_s<f32s_f64a>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
+  return launch_batch_s<__half>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
 }
 
 template <typename S>
@@ -1099,6 +1105,7 @@ struct lbm_batch {
   RunDev* d_runs;
   Item* d_items;
   int nitems, items_cap;
+  int total_rows;  // balanced schedule: rows of all strip items (0 for item lists)
   unsigned long long* flags;
   unsigned long long* ctr;
   double* aux;
@@ -1156,18 +1163,23 @@ BatchLayout batch_layout(int n, const lbm_params* p) {
 int batch_items(lbm_batch* b, const Tile& t) {
   std::vector<Item> items;
   const int SW = 64 * t.nw;
+  int64_t rows = 0;
   for (int r = 0; r < b->nruns; ++r) {
     const int nx = b->p[r].nx, ny = b->p[r].ny;
-    const int L = t.L > 0 ? t.L : std::min(ny, LMAX);
+    const int L = t.L > 0 ? t.L : ny;  // L = 0: whole strips, balanced over the grid
     const int ns = t.ts == 2 ? (nx + SW - 7) / (SW - 6) : (nx + SW - 1) / SW;
     for (int y0 = 0; y0 < ny; y0 += L)
       for (int sx = 0; sx < ns; ++sx) {
         const int x0 = t.ts == 2 ? (int)((int64_t)sx * nx / ns) : sx * SW;
         const int x1 = t.ts == 2 ? (int)((int64_t)(sx + 1) * nx / ns) : std::min(nx, x0 + SW);
-        items.push_back(Item{r, x0, y0, x1 - x0, std::min(L, ny - y0), 0});
+        const int n = std::min(L, ny - y0);
+        items.push_back(Item{r, x0, y0, x1 - x0, n, t.L > 0 ? 0 : (int)rows});
+        rows += n;
       }
   }
   if ((int)items.size() > b->items_cap) return LBM_ENOSPACE;
+  if (rows >= INT32_MAX) return LBM_EINVAL;
+  b->total_rows = t.L > 0 ? 0 : (int)rows;
   HIPCHK(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, b->st));
   HIPCHK(hipStreamSynchronize(b->st));
   b->nitems = (int)items.size();
@@ -1190,7 +1202,7 @@ int batch_capture(lbm_batch* b, int parity) {
   const int launches = b->graph_k / b->tile.ts;  // graph_k is even
   for (int i = 0; i < launches && e == hipSuccess; ++i) {
     const int s = (parity + i) & 1;
-    e = launch_batch(b->prec, b->tile, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+    e = launch_batch(b->prec, b->tile, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems, b->total_rows,
                      b->ctr, (unsigned long long)i * b->tile.ts, b->flags, b->st);
   }
   if (e == hipSuccess) {
@@ -1363,7 +1375,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
     const int s = b->cur;
     Tile t = b->tile;
     if (n - done < t.ts) t.ts = 1;  // odd remainder of a two-step tile (its items suit both)
-    HIPCHK(launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems,
+    HIPCHK(launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems, b->total_rows,
                         nullptr, (unsigned long long)b->step, b->flags, b->st));
     b->cur ^= 1;
     b->step += t.ts;
@@ -1429,7 +1441,7 @@ int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth
         b->st,
         [&] {
           return launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items,
-                              b->nitems, nullptr, (unsigned long long)b->step, b->flags, b->st);
+                              b->nitems, b->total_rows, nullptr, (unsigned long long)b->step, b->flags, b->st);
         },
         5);
     if (ms < 0) return LBM_EHIP;
