@@ -366,10 +366,16 @@ def slab64_leg(lbm, torch, steps=10000):
 def batched_leg(lbm, torch, batch_steps, graph_steps):
     """256 uneven flat-interface runs (Lx in 64..512 step 32, Ly in 16..64 step 16,
     T/Tc in [0.5, 0.95], tau in [0.6, 1.5], sigma in [0, 0.2], C-S): one persistent
-    launch per step, in FP32 deviations (FP32 and FP64 collision arithmetic), in
-    plain FP32 populations with FP64 collision arithmetic (rho_ref = 0) and in FP64,
-    against the same runs through the plain FP64 path (one context per run, run
-    after run).  Coexistence densities are averaged over the last 4000 steps."""
+    launch per step (tuned tile) in FP64 and in three FP32-storage forms, and the FP64
+    runs through the plain path (one context per run, run after run).
+
+    FP32 forms: `f32` -- plain FP32 populations (rho_ref = 0) with FP32 collision
+    arithmetic, the headline; `f32dev` -- FP32 deviations from the mean density with
+    FP32 arithmetic; `f32_f64arith` -- plain FP32 populations with FP64 collision
+    arithmetic.  In both FP32-arithmetic forms the node's mass and momentum change
+    are restored in FP64 after the collision.  The headline ratio is `f32` batched
+    over FP64 batched; the ratio over the plain FP64 path is reported beside it.
+    Coexistence densities after batch_steps steps are averaged over the last 4000."""
     import numpy as np
 
     import synth
@@ -377,8 +383,9 @@ def batched_leg(lbm, torch, batch_steps, graph_steps):
     runs = synth.sweep_runs(256)
     nodes = sum(r["nx"] * r["ny"] for r in runs)
     res = {"runs": 256, "nodes": nodes, "coexistence_steps": batch_steps}
-    for name, prec, rr in (("f32dev", 1, float("nan")), ("f32dev_f64arith", 3, float("nan")),
-                           ("f32_f64arith_rhoref0", 3, 0.0), ("f64", 0, float("nan"))):
+    cases = {"f64": (0, float("nan")), "f32": (1, 0.0), "f32dev": (1, float("nan")),
+             "f32_f64arith": (3, 0.0)}
+    for name, (prec, rr) in cases.items():
         ps, rhos = surrogate.slab_runs(runs, prec, rho_ref=rr)
         b = lbm.Batch(ps, rhos)
         b.tune()
@@ -410,31 +417,24 @@ def batched_leg(lbm, torch, batch_steps, graph_steps):
         lat.close()
     res["f64_plain_mlups"] = round(nodes * 200 / wall / 1e6, 1)
     log(f"plain FP64 path: {res['f64_plain_mlups']} MLUPS")
-    for name in ("f32dev", "f32dev_f64arith", "f32_f64arith_rhoref0"):
-        res[f"ratio_{name}_batched_vs_f64_plain"] = round(
-            res[f"{name}_batched_mlups"] / res["f64_plain_mlups"], 2)
+    for name in ("f32", "f32dev", "f32_f64arith"):
         res[f"ratio_{name}_batched_vs_f64_batched"] = round(
             res[f"{name}_batched_mlups"] / res["f64_batched_mlups"], 2)
-    # coexistence densities after batch_steps, FP32 storage vs FP64.  Deviations from the mean
-    # density (rho_ref = NaN) and plain populations (rho_ref = 0, the same kernels): with
-    # density ratios up to 10^4 the vapour populations are far below w rho_mean, and the
-    # plain form keeps their relative precision.
-    cases = {"f64": (0, float("nan")), "f32dev": (1, float("nan")), "f32dev_f64arith": (3, float("nan")),
-             "f32_f64arith_rhoref0": (3, 0.0)}
+        res[f"ratio_{name}_batched_vs_f64_plain"] = round(
+            res[f"{name}_batched_mlups"] / res["f64_plain_mlups"], 2)
     out = {n: surrogate.run_batch(runs, batch_steps, prec, window=4000, samples=20, rho_ref=rr)
            for n, (prec, rr) in cases.items()}
     ref = out["f64"]
     res["diverged_f64"] = int(np.sum(ref["status"] != 0))
-    for n in ("f32dev", "f32dev_f64arith", "f32_f64arith_rhoref0"):
+    for n in ("f32", "f32dev", "f32_f64arith"):
         o = out[n]
         ok = (ref["status"] == 0) & (o["status"] == 0)
         err = np.maximum(np.abs(o["rho_l"][ok] / ref["rho_l"][ok] - 1), np.abs(o["rho_g"][ok] / ref["rho_g"][ok] - 1))
-        settled = ref["spread"][ok] < 1e-3
         res[f"{n}_diverged"] = int(np.sum(o["status"] != 0))
         res[f"{n}_coex_rel_err_median"] = float(np.median(err))
-        res[f"{n}_runs_within_1e-4"] = f"{int(np.sum(err <= 1e-4))}/{int(ok.sum())}"
-        res[f"{n}_settled_runs_within_1e-4"] = f"{int(np.sum(err[settled] <= 1e-4))}/{int(settled.sum())}"
         res[f"{n}_coex_rel_err_p90"] = float(np.quantile(err, 0.9))
+        res[f"{n}_coex_rel_err_max"] = float(err.max())
+        res[f"{n}_runs_within_1e-4"] = f"{int(np.sum(err <= 1e-4))}/{int(ok.sum())}"
         log(f"coexistence {n}: median {res[f'{n}_coex_rel_err_median']:.2e}, within 1e-4 "
             f"{res[f'{n}_runs_within_1e-4']}")
     return res

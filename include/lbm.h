@@ -253,6 +253,12 @@ int lbm_set_mrt(lbm_ctx* c, const double* rates);
  * timed lbm_step call captured none). */
 int lbm_graph_captures(lbm_ctx* c, int64_t* n);
 
+/* Index-checked builds only (liblbm_hip_check.so, compiled with
+ * LBM_CHECK_INDEX): the number of out-of-range global accesses or tile shapes
+ * the kernels have met since the last call (the accesses were skipped), then
+ * reset to 0.  Synchronises the device.  Release builds return LBM_ENOTSUP. */
+int lbm_debug_index_faults(uint64_t* count);
+
 /* The context's parameters, with rho_ref resolved (the mean initial density
  * when NaN was given; 0 for FP64 storage). */
 int lbm_get_params(lbm_ctx* c, lbm_params* out);

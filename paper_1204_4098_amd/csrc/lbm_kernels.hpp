@@ -34,6 +34,8 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "host_layout.hpp"  // Item
+
 namespace lbm {
 
 constexpr int LMAX = 128;  // largest chunk height (rows) k_step marches (halo arrays in LDS)
@@ -43,6 +45,7 @@ struct RunDev {
   int32_t nx, ny, pitch, eos;
   int64_t plane;            // elements between direction a and a+1 at one node
   int64_t rs;               // elements between row y and y+1 of one direction
+  int64_t elems;            // elements of the lattice's population buffer
   int64_t off;              // element offset of this lattice in the population pool
   double RT, c1, c2;        // EOS constants (see EosConst)
   double two_over_G, mG;    // 2/G and -G
@@ -62,12 +65,6 @@ struct RunDev {
   double s_e, s_eps, s_q, sig_e, sig_eps;
 };
 
-// A tile of the batched launch.  In the balanced schedule an item is a whole
-// strip of one run and row0 is its first row in the concatenated row space of
-// all items (rows of earlier items summed); item lists leave it 0.
-struct Item {
-  int32_t run, x0, y0, ncols, nrows, row0;
-};
 
 // Balanced schedule of a batch: the concatenated rows of all strips, [0,
 // total), are split evenly over the grid; block t (XCD-remapped) marches its
@@ -141,6 +138,29 @@ template <> struct Store<__half> {
   static __device__ __forceinline__ R round(R v) { return __half2float(__float2half_rn(v)); }
 };
 
+// Index-checked build (LBM_CHECK_INDEX): every global load and store of the
+// step, copy and mass kernels checks its element offset against the lattice's
+// buffer, and every tile its shape against the kernel's limits; a violation
+// is counted in g_index_faults (read by lbm_debug_index_faults) and the access
+// is skipped.  Release builds compile none of this.
+#ifdef LBM_CHECK_INDEX
+__device__ unsigned long long g_index_faults;
+__device__ __forceinline__ bool index_ok(int64_t off, int64_t n) {
+  if (off >= 0 && off < n) return true;
+  atomicAdd(&g_index_faults, 1ull);
+  return false;
+}
+#define LBM_TILE_CHECK(cond)                            \
+  do {                                                  \
+    if (!(cond)) atomicAdd(&g_index_faults, 1ull);      \
+  } while (0)
+#else
+__device__ __forceinline__ bool index_ok(int64_t, int64_t) { return true; }
+#define LBM_TILE_CHECK(cond) \
+  do {                       \
+  } while (0)
+#endif
+
 // D2Q9 directions e0=(0,0), e1=(1,0), e2=(0,1), e3=(-1,0), e4=(0,-1), e5=(1,1),
 // e6=(-1,1), e7=(-1,-1), e8=(1,-1) (pull9, collide and the moments use this
 // numbering); weights of Eq. (2):
@@ -178,6 +198,12 @@ __device__ __forceinline__ void pull9(const typename Store<S>::E* __restrict__ s
   const typename T::E* r0 = src + (int64_t)y * d.rs;
   const typename T::E* rm = src + (int64_t)ym * d.rs;
   const typename T::E* rp = src + (int64_t)yp * d.rs;
+#ifdef LBM_CHECK_INDEX
+  const typename T::E* p9[9] = {r0 + c.x,         r0 + P + c.xm,     rm + 2 * P + c.x,
+                                r0 + 3 * P + c.xp, rp + 4 * P + c.x,  rm + 5 * P + c.xm,
+                                rm + 6 * P + c.xp, rp + 7 * P + c.xp, rp + 8 * P + c.xm};
+  for (int a = 0; a < 9; ++a) f[a] = index_ok(p9[a] - src, d.elems) ? T::ld(p9[a]) : typename T::R(0);
+#else
   f[0] = T::ld(r0 + c.x);
   f[1] = T::ld(r0 + P + c.xm);
   f[2] = T::ld(rm + 2 * P + c.x);
@@ -187,6 +213,7 @@ __device__ __forceinline__ void pull9(const typename Store<S>::E* __restrict__ s
   f[6] = T::ld(rm + 6 * P + c.xp);
   f[7] = T::ld(rp + 7 * P + c.xp);
   f[8] = T::ld(rp + 8 * P + c.xm);
+#endif
 }
 
 // The arithmetic of one node update below is written with explicit fma()
@@ -452,6 +479,8 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
   using R = typename T::R;
   constexpr int SW = 64 * NW;
   const int tid = threadIdx.x;
+  LBM_TILE_CHECK(ncols >= 1 && ncols <= SW && nrows >= 1 && nrows <= LMAX && x0 >= 0 &&
+                 x0 + ncols <= d.nx && y0 >= 0 && y0 + nrows <= d.ny);
   const bool act = tid < ncols;
   const int x = x0 + tid;
   const Cols cx = cols_of(act ? x : x0, d.nx);
@@ -521,7 +550,8 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
       update_node<S, MRT>(fc, drho, rho64, Fx, Fy, ip2, d);
       typename T::E* row = dst + (int64_t)y * d.rs;
 #pragma unroll
-      for (int a = 0; a < 9; ++a) T::st(row + a * d.plane + cx.x, fc[a]);
+      for (int a = 0; a < 9; ++a)
+        if (index_ok(row + a * d.plane + cx.x - dst, d.elems)) T::st(row + a * d.plane + cx.x, fc[a]);
 #pragma unroll
       for (int a = 0; a < 9; ++a) fc[a] = fn[a];
       psi2c = psi2n;
@@ -548,7 +578,8 @@ __device__ __forceinline__ void copy_tile(const typename Store<S>::E* __restrict
   for (int j = 0; j < nrows; ++j) {
     const int64_t o = (int64_t)(y0 + j) * d.rs + x;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) dst[o + a * d.plane] = src[o + a * d.plane];
+    for (int a = 0; a < 9; ++a)
+      if (index_ok(o + a * d.plane, d.elems)) dst[o + a * d.plane] = src[o + a * d.plane];
   }
 }
 
@@ -649,6 +680,8 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   using T = Store<S>;
   using R = typename T::R;
   const int tid = threadIdx.x;
+  LBM_TILE_CHECK(ncols >= 1 && ncols <= 64 * NW - 6 && nrows >= 1 && x0 >= 0 &&
+                 x0 + ncols <= d.nx && y0 >= 0 && y0 + nrows <= d.ny);
   const int n0 = ncols + 6;                         // lanes that evaluate psi(t)
   const bool act0 = tid < n0;
   const bool act1 = tid >= 1 && tid < n0 - 1;       // lanes that run step one
@@ -776,7 +809,8 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
       if (out) {
         typename T::E* orow = dst + (int64_t)wrapy(r) * d.rs;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) T::st(orow + a * d.plane + cx.x, hp[a]);
+        for (int a = 0; a < 9; ++a)
+          if (index_ok(orow + a * d.plane + cx.x - dst, d.elems)) T::st(orow + a * d.plane + cx.x, hp[a]);
       }
     }
     if (St || j >= 3) {
@@ -811,13 +845,6 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   if (__lane_id() == 0 && (b1 | b2) != 0) atomicMin(flag, b1 != 0 ? step : step + 1);
 }
 
-// Order of the balanced schedule's row space per storage type: strip-major,
-// or band-major (eight horizontal bands of rows, each strip's rows of a band
-// contiguous), which gives the blocks of one XCD one band of all strips.
-// Measured on the 4096 x 4096 droplet workload: band-major is 2 % faster for
-// FP64 storage and 3 % slower for FP32 storage with FP64 arithmetic.
-template <typename S> struct Step2BandMajor : std::false_type {};
-template <> struct Step2BandMajor<double> : std::true_type {};
 // Strip edges of the two-step kernel are rounded down to multiples of this
 // many columns (FP64: 8 columns = 64 B, so no 64-byte segment of a population
 // row is written by two blocks; 3 % faster on the 4096 x 4096 droplet
@@ -829,8 +856,10 @@ template <> struct Step2Align<double> : std::integral_constant<int, 8> {};
 // Two steps per launch over the single lattice; strips of at most 64*NW - 6
 // columns, spread evenly over nx (edges aligned as Step2Align says).  L > 0: one block per (strip, L-row chunk);
 // L == 0: balanced schedule, every block marches one contiguous share of the
-// row space in the order above (no length cap: the tile holds no per-row
-// arrays); a share is split where it crosses a strip or band boundary.
+// strip-major row space (no length cap: the tile holds no per-row arrays); a
+// share is split where it crosses a strip boundary.  (With the row-interleaved
+// layout a band-major order -- the blocks of one XCD marching one band of rows
+// across all strips -- measured no faster for any storage type.)
 template <typename S, int NW, int PF>
 __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* __restrict__ src,
                                                    typename Store<S>::E* __restrict__ dst,
@@ -868,25 +897,9 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
   const int64_t total = (int64_t)nstrips * d.ny;
   int64_t r = total * t / gridDim.x;
   const int64_t e = total * (t + 1) / gridDim.x;
-  auto bstart = [&](int k) { return (int)((int64_t)k * d.ny / 8); };
   while (r < e) {
-    int s, y, n;
-    if constexpr (Step2BandMajor<S>::value) {
-      // band-major order: 8 horizontal bands of rows, then strip, then row
-      int k = (int)(r * 8 / total);
-      while (k > 0 && (int64_t)nstrips * bstart(k) > r) --k;
-      while (k < 7 && (int64_t)nstrips * bstart(k + 1) <= r) ++k;
-      const int b0 = bstart(k), rows = bstart(k + 1) - b0;
-      const int64_t rr = r - (int64_t)nstrips * b0;
-      s = (int)(rr / rows);
-      y = b0 + (int)(rr - (int64_t)s * rows);
-      n = (int)min(e - r, (int64_t)(b0 + rows - y));
-    } else {
-      // strip-major order
-      s = (int)(r / d.ny);
-      y = (int)(r - (int64_t)s * d.ny);
-      n = (int)min(e - r, (int64_t)(d.ny - y));
-    }
+    const int s = (int)(r / d.ny), y = (int)(r - (int64_t)s * d.ny);
+    const int n = (int)min(e - r, (int64_t)(d.ny - y));
     int x0, nc;
     strip(s, x0, nc);
     if (frozen)
@@ -1157,7 +1170,8 @@ __global__ __launch_bounds__(256) void k_mass(const typename Store<S>::E* __rest
                             3 * P + r0 + xp, 4 * P + rp + x,  5 * P + rm + xm,
                             6 * P + rm + xp, 7 * P + rp + xp, 8 * P + rp + xm};
     double r = 0.0;
-    for (int a = 0; a < 9; ++a) r += decode(src[idx[a]], a, d.rho_ref);
+    for (int a = 0; a < 9; ++a)
+      if (index_ok(idx[a], d.elems)) r += decode(src[idx[a]], a, d.rho_ref);
     acc_i += __double2ll_rn(r * 1099511627776.0);  // 2^40, exact scaling
     acc_d += r;
   }

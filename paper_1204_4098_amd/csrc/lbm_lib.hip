@@ -43,19 +43,10 @@ struct Tile {
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int esize_of(int prec) { return prec == LBM_PREC_F64 ? 8 : prec == LBM_PREC_F16DEV ? 2 : 4; }
-int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
-
-// Population storage, row-interleaved: element (a, y, x) at a * plane + y * rs
-// + x with rows of pitch elements (nx rounded up to 64), plane = pitch and rs =
-// 9 pitch, so the nine direction rows of one lattice row are consecutive in
-// memory.  A row of the march then reads and writes three 9-row blocks close
-// together instead of 18 rows in nine planes far apart: on the 4096 x 4096
-// FP64 workload the two-step kernel runs 491 us per launch against 525 us with
-// plane-major storage (plane = ny pitch, rs = pitch), and a memory-only
-// marching probe reaches 5.5 against 5.2 TB/s.
-int64_t plane_of(int nx) { return (int64_t)pitch_of(nx); }
-int64_t rs_of(int nx) { return 9 * (int64_t)pitch_of(nx); }
-int64_t elems_of(int nx, int ny) { return 9 * (int64_t)pitch_of(nx) * ny; }
+using layout::elems_of;
+using layout::pitch_of;
+using layout::plane_of;
+using layout::rs_of;
 
 int validate(const lbm_params& p) {
   if (p.nx < 3 || p.ny < 3) return LBM_EINVAL;
@@ -90,6 +81,7 @@ RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64
   d.eos = p.eos;
   d.plane = plane_of(p.nx);
   d.rs = rs_of(p.nx);
+  d.elems = elems_of(p.nx, p.ny);
   d.off = off;
   d.RT = k.RT;
   d.c1 = k.c1;
@@ -155,53 +147,38 @@ void set_mrt(RunDev& d, const lbm_params& p, const double* r) {
   d.sig_eps = p.sigma / (1.0 / r[1] - 0.5);
 }
 
-// Encode FP64 populations f[a][y][x] into the pre-streamed storage buffer:
-// buf[a][y][x] holds f*_a(x, y), and the kernel's pull reads it at node
-// (x + e_a, y + e_a); so buf[a][y][x] = f[a][y + ey][x + ex] (periodic).
+// Encode FP64 populations into the storage buffer (layout::encode): FP64 as
+// is, deviations f - w rho_ref rounded to FP32 (and then to FP16).
 template <typename S>
 void encode_buffer(const lbm_params& p, double rref, const double* f, std::vector<char>& out) {
-  const size_t plane = plane_of(p.nx), rs = rs_of(p.nx), n = (size_t)p.nx * p.ny;
   out.assign(elems_of(p.nx, p.ny) * sizeof(S), 0);
   S* b = reinterpret_cast<S*>(out.data());
-  for (int a = 0; a < 9; ++a)
-    for (int y = 0; y < p.ny; ++y) {
-      const int ys = (y + kEYh[a] + p.ny) % p.ny;
-      for (int x = 0; x < p.nx; ++x) {
-        const int xs = (x + kEXh[a] + p.nx) % p.nx;
-        const double v = f[a * n + (size_t)ys * p.nx + xs];
-        if constexpr (std::is_same<S, double>::value)
-          b[a * plane + (size_t)y * rs + x] = v;
-        else if constexpr (std::is_same<S, float>::value)
-          b[a * plane + (size_t)y * rs + x] = (float)(v - kWh[a] * rref);
-        else  // RNE to FP32, then RNE to FP16
-          b[a * plane + (size_t)y * rs + x] = __float2half_rn((float)(v - kWh[a] * rref));
-      }
-    }
+  layout::encode(p.nx, p.ny, f, b, [&](int a, double v) -> S {
+    if constexpr (std::is_same<S, double>::value)
+      return v;
+    else if constexpr (std::is_same<S, float>::value)
+      return (float)(v - kWh[a] * rref);
+    else  // RNE to FP32, then RNE to FP16
+      return __float2half_rn((float)(v - kWh[a] * rref));
+  });
 }
 
+// Decode the storage buffer to FP64 populations: f = s + (w rho_ref), two
+// separately rounded operations (as the device decoder of the mass does).
 template <typename S>
 void decode_buffer(const lbm_params& p, double rref, const char* raw, double* f) {
-  const size_t plane = plane_of(p.nx), rs = rs_of(p.nx), n = (size_t)p.nx * p.ny;
   const S* b = reinterpret_cast<const S*>(raw);
-  for (int a = 0; a < 9; ++a)
-    for (int y = 0; y < p.ny; ++y) {
-      const int ys = (y - kEYh[a] + p.ny) % p.ny;
-      for (int x = 0; x < p.nx; ++x) {
-        const int xs = (x - kEXh[a] + p.nx) % p.nx;
-        const S v = b[a * plane + (size_t)ys * rs + xs];
-        double d;
-        if constexpr (std::is_same<S, double>::value) {
-          d = v;
-        } else {
-          volatile double wr = kWh[a] * rref;  // keep the two roundings separate
-          if constexpr (std::is_same<S, float>::value)
-            d = (double)v + wr;
-          else
-            d = (double)__half2float(v) + wr;
-        }
-        f[a * n + (size_t)y * p.nx + x] = d;
-      }
+  layout::decode(p.nx, p.ny, b, f, [&](int a, S v) -> double {
+    if constexpr (std::is_same<S, double>::value) {
+      return v;
+    } else {
+      volatile double wr = kWh[a] * rref;  // keep the two roundings separate
+      if constexpr (std::is_same<S, float>::value)
+        return (double)v + wr;
+      else
+        return (double)__half2float(v) + wr;
     }
+  });
 }
 
 void encode_any(int prec, const lbm_params& p, double rref, const double* f, std::vector<char>& o) {
@@ -894,6 +871,7 @@ int lbm_mass_noalloc(const void* dev_populations, int32_t nx, int32_t ny, int32_
   d.pitch = pitch_of(nx);
   d.plane = plane_of(nx);
   d.rs = rs_of(nx);
+  d.elems = elems_of(nx, ny);
   d.rho_ref = precision == LBM_PREC_F64 ? 0.0 : rho_ref;
   __int128* pi = reinterpret_cast<__int128*>(base);
   double* pd = reinterpret_cast<double*>(pi + kMassBlocks);
@@ -1063,6 +1041,21 @@ int lbm_graph_captures(lbm_ctx* c, int64_t* n) {
   return LBM_OK;
 }
 
+int lbm_debug_index_faults(uint64_t* count) {
+  if (!count) return LBM_EINVAL;
+#ifdef LBM_CHECK_INDEX
+  unsigned long long v = 0, zero = 0;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_index_faults), sizeof v));
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(g_index_faults), &zero, sizeof zero));
+  *count = v;
+  return LBM_OK;
+#else
+  *count = 0;
+  return LBM_ENOTSUP;
+#endif
+}
+
 int lbm_get_params(lbm_ctx* c, lbm_params* out) {
   if (!c || !out) return LBM_EINVAL;
   *out = c->p;
@@ -1128,9 +1121,7 @@ struct BatchLayout {
   size_t aux_nodes;
 };
 
-int64_t run_elems(const lbm_params& q) {
-  return (elems_of(q.nx, q.ny) + 63) / 64 * 64;
-}
+int64_t run_elems(const lbm_params& q) { return layout::run_elems(q.nx, q.ny); }
 
 BatchLayout batch_layout(int n, const lbm_params* p) {
   BatchLayout L{};
@@ -1140,8 +1131,7 @@ BatchLayout batch_layout(int n, const lbm_params* p) {
   for (int i = 0; i < n; ++i) {
     elems += run_elems(p[i]);
     maxn = std::max(maxn, (size_t)p[i].nx * p[i].ny);
-    // the most items any offered tile can produce (1 wave, 4 rows)
-    cap += ((p[i].nx + 63) / 64) * ((p[i].ny + 3) / 4);
+    cap += layout::max_items(p[i].nx, p[i].ny);
   }
   L.pool = align_up(elems * es);
   L.runs = align_up(n * sizeof(RunDev));
@@ -1155,28 +1145,15 @@ BatchLayout batch_layout(int n, const lbm_params* p) {
   return L;
 }
 
-// Work list: tiles of every run; L = 0 means one item per whole strip column.
-// Work list of a tile: per run, chunks of L rows (at most LMAX) times strips of
-// 64*nw columns, or for the two-step tile strips of at most 64*nw - 6 columns
-// spread evenly over the run's width (such items also suit the one-step
-// kernel, which runs an odd remainder step).
+// Work list of a tile (layout::build_items), uploaded to the device.
 int batch_items(lbm_batch* b, const Tile& t) {
   std::vector<Item> items;
-  const int SW = 64 * t.nw;
-  int64_t rows = 0;
+  std::vector<int> nx(b->nruns), ny(b->nruns);
   for (int r = 0; r < b->nruns; ++r) {
-    const int nx = b->p[r].nx, ny = b->p[r].ny;
-    const int L = t.L > 0 ? t.L : ny;  // L = 0: whole strips, balanced over the grid
-    const int ns = t.ts == 2 ? (nx + SW - 7) / (SW - 6) : (nx + SW - 1) / SW;
-    for (int y0 = 0; y0 < ny; y0 += L)
-      for (int sx = 0; sx < ns; ++sx) {
-        const int x0 = t.ts == 2 ? (int)((int64_t)sx * nx / ns) : sx * SW;
-        const int x1 = t.ts == 2 ? (int)((int64_t)(sx + 1) * nx / ns) : std::min(nx, x0 + SW);
-        const int n = std::min(L, ny - y0);
-        items.push_back(Item{r, x0, y0, x1 - x0, n, t.L > 0 ? 0 : (int)rows});
-        rows += n;
-      }
+    nx[r] = b->p[r].nx;
+    ny[r] = b->p[r].ny;
   }
+  const int64_t rows = layout::build_items(b->nruns, nx.data(), ny.data(), t.nw, t.L, t.ts, items);
   if ((int)items.size() > b->items_cap) return LBM_ENOSPACE;
   if (rows >= INT32_MAX) return LBM_EINVAL;
   b->total_rows = t.L > 0 ? 0 : (int)rows;

@@ -16,6 +16,7 @@ import torch  # loaded first, so the library binds to the HIP runtime torch alre
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
+LIB_CHECK_PATH = os.path.join(HERE, "liblbm_hip_check.so")   # index-checked build (tests)
 
 LBM_OK, LBM_EINVAL, LBM_EPSI, LBM_EDIVERGED, LBM_EHIP, LBM_ENOSPACE, LBM_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 LBM_EOS_CS, LBM_EOS_PR = 0, 1
@@ -72,6 +73,7 @@ _SIGS = {
     "lbm_set_mrt": (C.c_int, [_vp, _vp]),
     "lbm_device_buffers": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), _ip]),
     "lbm_get_params": (C.c_int, [_vp, _P]),
+    "lbm_debug_index_faults": (C.c_int, [C.POINTER(C.c_uint64)]),
     "lbm_destroy": (C.c_int, [_vp]),
     "lbm_batch_workspace_bytes": (C.c_int, [C.c_int32, _P, C.POINTER(C.c_size_t)]),
     "lbm_batch_init": (C.c_int, [C.c_int32, _P, C.POINTER(_vp), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
@@ -89,19 +91,25 @@ _SIGS = {
 }
 
 
+def load(path: str):
+    """Load a build of the library and declare its C signatures; raises if it has
+    not been built (there is no CPU fallback)."""
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    L = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
 def lib():
-    """The loaded library; raises if it has not been built (no fallback)."""
+    """The loaded library (the release build)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                               "(there is no CPU fallback)")
-        L = C.CDLL(LIB_PATH)
-        for name, (res, args) in _SIGS.items():
-            fn = getattr(L, name)
-            fn.restype = res
-            fn.argtypes = args
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
 
 

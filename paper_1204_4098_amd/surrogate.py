@@ -94,10 +94,12 @@ def run_batch(runs, steps, precision=lbm.LBM_PREC_F32DEV, graph_steps=100, tune=
 
 
 def dataset(nruns, steps, precision=lbm.LBM_PREC_F32DEV, batch=256, seed=synth.BASE_SEED,
-            t_range=(0.5, 0.95), max_spread=0.02, rho_ref=math.nan, log=None):
+            t_range=(0.5, 0.95), max_spread=0.02, rho_ref=0.0, log=None):
     """Sweep runs drawn as in the batched coexistence sweep; X = (T/Tc, tau, sigma),
     Y = (log rho_l, log rho_g) (time-averaged) of the runs that stayed finite and
-    whose snapshots over the averaging window spread by less than max_spread."""
+    whose snapshots over the averaging window spread by less than max_spread.  By
+    default the populations are stored as plain FP32 values (rho_ref = 0) with FP32
+    collision arithmetic (mass and momentum change restored in FP64 per node)."""
     X, Y, ndiv, nmov, secs, lups = [], [], 0, 0, 0.0, 0
     for k in range(0, nruns, batch):
         runs = synth.sweep_runs(min(batch, nruns - k), seed=seed + k, t_range=t_range)
