@@ -159,6 +159,13 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="waves,rows,depth[,steps]: fixed launch shape (no tuning); steps = time "
                          "steps per launch (1, or 2 for the two-step kernel)")
+    ap.add_argument("--batch-case", default=None, choices=["f64", "f32", "f32dev", "f32_f64arith"],
+                    help="time only this case of the batched leg (no plain-path timing, no "
+                         "coexistence comparison): a short run for the counter profiles")
+    ap.add_argument("--batch-tile", default=None,
+                    help="waves,rows,depth,steps: fixed batch tile (no tuning)")
+    ap.add_argument("--batch-time-steps", type=int, default=2000,
+                    help="timed steps of each batched case")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a known-size kernel "
                          "for scaling memory counters)")
@@ -244,7 +251,9 @@ def main():
         out["slab64"] = slab64_leg(lbm, torch)
         log(f"slab64 leg: {out['slab64']}")
     if "batched" in legs:
-        out["batched"] = batched_leg(lbm, torch, args.batch_steps, args.graph_steps)
+        btile = tuple(int(v) for v in args.batch_tile.split(",")) if args.batch_tile else None
+        out["batched"] = batched_leg(lbm, torch, args.batch_steps, args.graph_steps, args.batch_case,
+                                     btile, args.batch_time_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(kw, rho0)
         if "batched" in legs:
@@ -282,10 +291,14 @@ def settle(lat, torch, ms):
 
 def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_steps, tune, tile=None,
                  settle_ms=100.0):
-    """Settle, warm up, then time `steps` steps between a device sync on both sides.
-    The settling steps and the warm-up steps advance the state but are not timed."""
+    """Settle, tune, capture, settle again, warm up, then time `steps` steps between a
+    device sync on both sides.  Settling before the autotuner lets it compare tiles
+    at sustained clocks; settling again after the graph capture (host work that
+    leaves the GPU idle) restores them for the timed steps.  None of these steps
+    is timed; all of them advance the state."""
     p = lbm.params(nx, ny, precision=precision, **kw)
     lat = lbm.Lattice(p, rho0, device="cuda:0")
+    settle(lat, torch, settle_ms)
     if tile:
         lat.set_tile(*tile)
     elif tune:
@@ -363,7 +376,7 @@ def slab64_leg(lbm, torch, steps=10000):
     return res
 
 
-def batched_leg(lbm, torch, batch_steps, graph_steps):
+def batched_leg(lbm, torch, batch_steps, graph_steps, only=None, tile=None, time_steps=2000):
     """256 uneven flat-interface runs (Lx in 64..512 step 32, Ly in 16..64 step 16,
     T/Tc in [0.5, 0.95], tau in [0.6, 1.5], sigma in [0, 0.2], C-S): one persistent
     launch per step (tuned tile) in FP64 and in three FP32-storage forms, and the FP64
@@ -375,7 +388,9 @@ def batched_leg(lbm, torch, batch_steps, graph_steps):
     arithmetic.  In both FP32-arithmetic forms the node's mass and momentum change
     are restored in FP64 after the collision.  The headline ratio is `f32` batched
     over FP64 batched; the ratio over the plain FP64 path is reported beside it.
-    Coexistence densities after batch_steps steps are averaged over the last 4000."""
+    Coexistence densities after batch_steps steps are averaged over the last 4000.
+    `only` restricts the leg to the timing of one case (with `tile` fixed, if given,
+    and `time_steps` timed steps), for short profiled runs."""
     import numpy as np
 
     import synth
@@ -386,21 +401,28 @@ def batched_leg(lbm, torch, batch_steps, graph_steps):
     cases = {"f64": (0, float("nan")), "f32": (1, 0.0), "f32dev": (1, float("nan")),
              "f32_f64arith": (3, 0.0)}
     for name, (prec, rr) in cases.items():
+        if only and name != only:
+            continue
         ps, rhos = surrogate.slab_runs(runs, prec, rho_ref=rr)
         b = lbm.Batch(ps, rhos)
-        b.tune()
+        if tile:
+            b.set_tile(*tile)
+        else:
+            b.tune()
         if graph_steps:
             b.set_graph_steps(100)
         b.step(200)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b.step(2000)
+        b.step(time_steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        res[f"{name}_batched_mlups"] = round(nodes * 2000 / wall / 1e6, 1)
+        res[f"{name}_batched_mlups"] = round(nodes * time_steps / wall / 1e6, 1)
         res[f"{name}_batched_tile"] = list(b.get_tile())
         b.close()
         log(f"batched {name}: {res[f'{name}_batched_mlups']} MLUPS")
+    if only:
+        return res
     # the plain FP64 path: one lattice context per run, each stepped in turn
     ps, rhos = surrogate.slab_runs(runs, 0)
     lats = [lbm.Lattice(p, r) for p, r in zip(ps, rhos)]

@@ -300,7 +300,7 @@ int lbm_batch_get_populations(lbm_batch* b, int32_t run, double* f);
  * over the grid; rows = 0: the balanced schedule, in which the rows of all
  * whole-run strips, concatenated, are split evenly over a grid sized to the
  * resident capacity), tuned over the whole batch like lbm_tune;
- * waves in {1, 2, 4, 8}; steps = 2 (waves 4 or 8) runs two time steps per
+ * waves in {1, 2, 4, 8}; steps = 2 (waves 2, 4 or 8) runs two time steps per
  * launch as for a single lattice, with strips of at most 64*waves - 6
  * columns. */
 int lbm_batch_tune(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);

@@ -54,8 +54,10 @@ struct RunDev {
   // F_a = w_a [3 Be e.F + Ce (9 (e.vf)(e.F) - 3 vf.F)], vf = u + c_f F/rho + sig F/psi^2
   double c_eq, c_f, sig, Be, Ce;
   // products used by the collision: w0 Ce, w1 Ce, w2 Ce and 3 w1 Be, 3 w2 Be
-  // (w0, w1, w2 = 4/9, 1/9, 1/36)
+  // (w0, w1, w2 = 4/9, 1/9, 1/36); om w0, om w1, om w2, 3 om w1, 3 om w2 and
+  // 1 - om with om = 1/tau
   double wCe0, wCe1, wCe2, wBe3_1, wBe3_2;
+  double om_w0, om_w1, om_w2, om_3w1, om_3w2, om1;
   double rho_ref;           // deviation reference density (0 for FP64 storage)
   int32_t run;
   int32_t mrt;              // 1: multiple-relaxation-time collision (collide_mrt)
@@ -103,11 +105,16 @@ __device__ __forceinline__ void balanced_pieces(const Item* __restrict__ items, 
 // show no difference.
 struct f32s_f64a {};  // FP32 deviation storage with FP64 collision arithmetic
 template <typename S> struct Store;
-// kConserve: after the FP32 collision, restore the node's mass and momentum
-// change exactly (see conserve()).
+// E: stored type; R: collision arithmetic; P: type of psi, of the force and of
+// the density they are evaluated at -- FP64, except with FP16 storage, whose
+// rounding of the populations (1e-3 of the deviations) is far above the 1e-6
+// relative error of an FP32 psi (see psi2_of).  kConserve: after the FP32
+// collision, restore the node's mass and momentum change exactly (see
+// conserve()).
 template <> struct Store<double> {
   using E = double;
   using R = double;
+  using P = double;
   static constexpr bool kConserve = false;
   static __device__ __forceinline__ R ld(const E* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(v, p); }
@@ -116,6 +123,7 @@ template <> struct Store<double> {
 template <> struct Store<float> {
   using E = float;
   using R = float;
+  using P = double;
   static constexpr bool kConserve = true;
   static __device__ __forceinline__ R ld(const E* p) { return *p; }
   static __device__ __forceinline__ void st(E* p, R v) { *p = v; }
@@ -124,6 +132,7 @@ template <> struct Store<float> {
 template <> struct Store<f32s_f64a> {
   using E = float;
   using R = double;
+  using P = double;
   static constexpr bool kConserve = false;
   static __device__ __forceinline__ R ld(const E* p) { return double(__builtin_nontemporal_load(p)); }
   static __device__ __forceinline__ void st(E* p, R v) { __builtin_nontemporal_store(float(v), p); }
@@ -132,10 +141,24 @@ template <> struct Store<f32s_f64a> {
 template <> struct Store<__half> {
   using E = __half;
   using R = float;
+  using P = float;
   static constexpr bool kConserve = false;
+  // The narrowing to FP16 takes its operand through an empty asm statement:
+  // the backend otherwise folds it into the FMA that produced the operand (a
+  // mixed-precision FMA with an FP16 result, one rounding instead of two) at
+  // some call sites only, whatever the contraction setting, which breaks the
+  // bitwise identity of the one- and two-step kernels.
+  static __device__ __forceinline__ _Float16 narrow(R v) {
+    asm volatile("" : "+v"(v));
+    return static_cast<_Float16>(v);
+  }
   static __device__ __forceinline__ R ld(const E* p) { return __half2float(*p); }
-  static __device__ __forceinline__ void st(E* p, R v) { *p = __float2half_rn(v); }
-  static __device__ __forceinline__ R round(R v) { return __half2float(__float2half_rn(v)); }
+  static __device__ __forceinline__ void st(E* p, R v) {
+    __half_raw h;
+    h.data = narrow(v);
+    *p = h;
+  }
+  static __device__ __forceinline__ R round(R v) { return static_cast<float>(narrow(v)); }
 };
 
 // Index-checked build (LBM_CHECK_INDEX): every global load and store of the
@@ -228,23 +251,33 @@ __device__ __forceinline__ R sum9(const R (&s)[9]) {
   return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
 }
 
-// psi^2 = 2 (p_EOS(rho) - rho/3) / G in FP64 (Eq. 8 with Eq. 23 or Peng-Robinson).
-__device__ __forceinline__ double psi2_of(double rho, const RunDev& d) {
+// psi^2 = 2 (p_EOS(rho) - rho/3) / G (Eq. 8 with Eq. 23 or Peng-Robinson), in
+// the type P.  Evaluated in FP32 from an FP32 density, psi differs from the
+// FP64 value by at most 1e-6 relative over 0.9 rho_v .. 1.02 rho_l at 0.5 to
+// 0.99 T_c (C-S a = 1, b = 4; P-R a = 2/49, b = 2/21, omega = 0.344).
+template <typename P>
+__device__ __forceinline__ P psi2_of(P rho, const RunDev& d) {
 #pragma clang fp contract(off)
-  double p;
+  P p;
+  const P one = P(1);
   if (d.eos == 0) {
     // rho RT (1 + e + e^2 - e^3)/(1 - e)^3 - c2 rho^2, e = b rho / 4
-    const double e = d.c1 * rho, m = 1.0 - e;
-    const double poly = fma(e, fma(e, 1.0 - e, 1.0), 1.0);
-    p = fma((rho * d.RT) * poly, rcp((m * m) * m), -((d.c2 * rho) * rho));
+    const P e = P(d.c1) * rho, m = one - e;
+    const P poly = fma(e, fma(e, one - e, one), one);
+    p = fma((rho * P(d.RT)) * poly, rcp((m * m) * m), -((P(d.c2) * rho) * rho));
   } else {
     // rho RT/(1 - b) - c2 rho^2/(1 + b(2 - b)) over one common reciprocal
-    const double b = d.c1 * rho;
-    const double q1 = 1.0 - b, q2 = fma(b, 2.0 - b, 1.0);
-    p = fma(rho * d.RT, q2, -(((d.c2 * rho) * rho) * q1)) * rcp(q1 * q2);
+    const P b = P(d.c1) * rho;
+    const P q1 = one - b, q2 = fma(b, P(2) - b, one);
+    p = fma(rho * P(d.RT), q2, -(((P(d.c2) * rho) * rho) * q1)) * rcp(q1 * q2);
   }
-  return fma(rho, -1.0 / 3.0, p) * d.two_over_G;
+  return fma(rho, P(-1.0 / 3.0), p) * P(d.two_over_G);
 }
+
+// psi from psi^2: the correctly rounded FP64 square root, or the FP32
+// hardware root (1 ulp; psi^2 is a positive normal number or NaN).
+__device__ __forceinline__ double psi_root(double x) { return sqrt(x); }
+__device__ __forceinline__ float psi_root(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 __device__ __forceinline__ double pressure_of(double rho, const RunDev& d) {
   if (d.eos == 0) {
@@ -256,15 +289,16 @@ __device__ __forceinline__ double pressure_of(double rho, const RunDev& d) {
 
 // Interaction force of Eq. (3) from the 3x3 psi neighbourhood (row-major:
 // s = y-1, c = y, n = y+1; index 0 = x-1, 1 = x, 2 = x+1), w(1)=1/3, w(2)=1/12.
-__device__ __forceinline__ void force3x3(const double* rs, const double* rc, const double* rn, int i,
-                                         double mG, double& Fx, double& Fy) {
+template <typename P>
+__device__ __forceinline__ void force3x3(const P* rs, const P* rc, const P* rn, int i, P mG, P& Fx,
+                                         P& Fy) {
 #pragma clang fp contract(off)
-  constexpr double w1 = 1.0 / 3.0, w2 = 1.0 / 12.0;
-  const double dNE = rn[i + 1] - rs[i - 1];   // psi(x+e5) - psi(x-e5)
-  const double dNW = rn[i - 1] - rs[i + 1];   // psi(x+e6) - psi(x-e6)
-  const double Sx = fma(w1, rc[i + 1] - rc[i - 1], w2 * (dNE - dNW));
-  const double Sy = fma(w1, rn[i] - rs[i], w2 * (dNE + dNW));
-  const double c = mG * rc[i];
+  const P w1 = P(1.0 / 3.0), w2 = P(1.0 / 12.0);
+  const P dNE = rn[i + 1] - rs[i - 1];   // psi(x+e5) - psi(x-e5)
+  const P dNW = rn[i - 1] - rs[i + 1];   // psi(x+e6) - psi(x-e6)
+  const P Sx = fma(w1, rc[i + 1] - rc[i - 1], w2 * (dNE - dNW));
+  const P Sy = fma(w1, rn[i] - rs[i], w2 * (dNE + dNW));
+  const P c = mG * rc[i];
   Fx = c * Sx;
   Fy = c * Sy;
 }
@@ -275,19 +309,20 @@ __device__ __forceinline__ void force3x3(const double* rs, const double* rc, con
 //   seq_a = w (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u))        (Eq. 2, deviation form)
 //   F_a   = w [3 B_e e.F + C_e (9 (e.v)(e.F) - 3 v.F)]             (Eq. 12)
 // The opposite direction (e -> -e) flips the odd terms only, so each pair is
-// evaluated once: seq = A +- B, F_a = C +- D, and s' = (s - om s) + (P +- Q) with
-// P = om A + C, Q = om B + D.
+// evaluated once: om seq = om w X +- 3 om w rho e.u with X = drho + rho (4.5
+// (e.u)^2 - 1.5 u.u), F_a = C +- D, and s' = (1 - om) s + (P +- Q) with
+// P = om w X + C, Q = 3 om w rho e.u + D (the products of om and the weights
+// are per-lattice constants).
 template <typename R>
-__device__ __forceinline__ void collide_pair(R& sa, R& sb, R eu, R eF, R ev, R w, R wr3, R wCe,
-                                             R wBe3, R rho, R drho, R usq, R vF3, R om) {
+__device__ __forceinline__ void collide_pair(R& sa, R& sb, R eu, R eF, R ev, R omw, R omwr3, R wCe,
+                                             R wBe3, R rho, R drho, R usq, R vF3, R om1) {
 #pragma clang fp contract(off)
-  const R A = w * fma(rho, fma(R(4.5) * eu, eu, -usq), drho);
-  const R B = wr3 * eu;
+  const R X = fma(rho, fma(R(4.5) * eu, eu, -usq), drho);
   const R C = wCe * fma(R(9) * ev, eF, -vF3);
-  const R D = wBe3 * eF;
-  const R P = fma(om, A, C), Q = fma(om, B, D);
-  sa = fma(-om, sa, sa) + (P + Q);
-  sb = fma(-om, sb, sb) + (P - Q);
+  const R P = fma(omw, X, C);
+  const R Q = fma(omwr3, eu, wBe3 * eF);
+  sa = fma(om1, sa, P + Q);
+  sb = fma(om1, sb, P - Q);
 }
 
 template <typename R>
@@ -300,24 +335,22 @@ __device__ __forceinline__ void collide(R (&s)[9], R drho, R rho, R jx, R jy, R 
   const R wx = fma(R(d.c_eq), Fr_x, ux), wy = fma(R(d.c_eq), Fr_y, uy);
   const R sg = R(d.sig) * inv_psi2;
   const R vx = fma(sg, Fx, fma(R(d.c_f), Fr_x, ux)), vy = fma(sg, Fy, fma(R(d.c_f), Fr_y, uy));
-  const R om = R(d.inv_tau);
+  const R om1 = R(d.om1);
   const R usq = R(1.5) * fma(wx, wx, wy * wy);
   const R vF3 = R(3) * fma(vx, Fx, vy * Fy);
-  const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w2 = R(1.0 / 36.0);
-  const R wr3_1 = R(3.0 / 9.0) * rho, wr3_2 = R(3.0 / 36.0) * rho;
+  const R omw1 = R(d.om_w1), omw2 = R(d.om_w2);
+  const R omwr3_1 = R(d.om_3w1) * rho, omwr3_2 = R(d.om_3w2) * rho;
   const R wCe1 = R(d.wCe1), wBe3_1 = R(d.wBe3_1), wCe2 = R(d.wCe2), wBe3_2 = R(d.wBe3_2);
   // rest direction: e = 0
-  {
-    const R A0 = w0 * fma(rho, -usq, drho);
-    const R C0 = R(d.wCe0) * -vF3;
-    s[0] = fma(-om, s[0], s[0]) + fma(om, A0, C0);
-  }
+  s[0] = fma(om1, s[0], fma(R(d.om_w0), fma(rho, -usq, drho), R(d.wCe0) * -vF3));
   // axis pairs (e1, e3 = -e1), (e2, e4 = -e2)
-  collide_pair(s[1], s[3], wx, Fx, vx, w1, wr3_1, wCe1, wBe3_1, rho, drho, usq, vF3, om);
-  collide_pair(s[2], s[4], wy, Fy, vy, w1, wr3_1, wCe1, wBe3_1, rho, drho, usq, vF3, om);
+  collide_pair(s[1], s[3], wx, Fx, vx, omw1, omwr3_1, wCe1, wBe3_1, rho, drho, usq, vF3, om1);
+  collide_pair(s[2], s[4], wy, Fy, vy, omw1, omwr3_1, wCe1, wBe3_1, rho, drho, usq, vF3, om1);
   // diagonal pairs (e5 = (1,1), e7 = -e5), (e6 = (-1,1), e8 = -e6)
-  collide_pair(s[5], s[7], wx + wy, Fx + Fy, vx + vy, w2, wr3_2, wCe2, wBe3_2, rho, drho, usq, vF3, om);
-  collide_pair(s[6], s[8], wy - wx, Fy - Fx, vy - vx, w2, wr3_2, wCe2, wBe3_2, rho, drho, usq, vF3, om);
+  collide_pair(s[5], s[7], wx + wy, Fx + Fy, vx + vy, omw2, omwr3_2, wCe2, wBe3_2, rho, drho, usq,
+               vF3, om1);
+  collide_pair(s[6], s[8], wy - wx, Fy - Fx, vy - vx, omw2, omwr3_2, wCe2, wBe3_2, rho, drho, usq,
+               vF3, om1);
 }
 
 // Multiple-relaxation-time collision with the improved forcing scheme, on the
@@ -407,17 +440,24 @@ __device__ __forceinline__ R mom_y(const R (&s)[9]) {
   return ((s[2] - s[4]) + (s[5] - s[7])) + (s[6] - s[8]);
 }
 
-// Mass and momentum of nine FP32 values summed in FP64 (exact unless the
+// Momentum of FP32 values (as FP64 t) summed in FP64: exact unless the
 // values span more than 29 binary orders of magnitude, and then wrong only by
-// an FP64 rounding of the largest, far below an FP32 rounding).
+// an FP64 rounding of the largest, far below an FP32 rounding; being exact,
+// the sums do not depend on their order.
+__device__ __forceinline__ void exact_momentum(const double (&t)[9], double& jx, double& jy) {
+#pragma clang fp contract(off)
+  const double u = t[5] - t[7], v = t[8] - t[6];
+  jx = ((t[1] - t[3]) + u) + v;
+  jy = ((t[2] - t[4]) + u) - v;
+}
+// Mass and momentum of nine FP32 values, exactly (as exact_momentum).
 __device__ __forceinline__ void exact_moments(const float (&s)[9], double& m, double& jx, double& jy) {
 #pragma clang fp contract(off)
   double t[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) t[a] = double(s[a]);
   m = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7])) + t[8];
-  jx = ((t[1] - t[3]) + (t[5] - t[7])) + (t[8] - t[6]);
-  jy = ((t[2] - t[4]) + (t[5] - t[7])) + (t[6] - t[8]);
+  exact_momentum(t, jx, jy);
 }
 
 // The collision conserves mass and changes the momentum by exactly F (every
@@ -431,16 +471,18 @@ __device__ __forceinline__ void exact_moments(const float (&s)[9], double& m, do
 // what remains is one FP32 rounding of five values.
 __device__ __forceinline__ void conserve(float (&s)[9], double m_t, double jx_t, double jy_t) {
 #pragma clang fp contract(off)
-  double jx, jy, m;
-  exact_moments(s, m, jx, jy);
-  const double dx = 0.5 * (jx_t - jx), dy = 0.5 * (jy_t - jy);
-  s[1] = float(double(s[1]) + dx);
-  s[3] = float(double(s[3]) - dx);
-  s[2] = float(double(s[2]) + dy);
-  s[4] = float(double(s[4]) - dy);
-  double t[9];
+  double t[9], jx, jy;
+  t[0] = 0.0;  // the rest population carries no momentum
 #pragma unroll
   for (int a = 1; a < 9; ++a) t[a] = double(s[a]);
+  exact_momentum(t, jx, jy);
+  const double dx = 0.5 * (jx_t - jx), dy = 0.5 * (jy_t - jy);
+  s[1] = float(t[1] + dx);
+  s[3] = float(t[3] - dx);
+  s[2] = float(t[2] + dy);
+  s[4] = float(t[4] - dy);
+#pragma unroll
+  for (int a = 1; a < 5; ++a) t[a] = double(s[a]);
   const double rest = ((t[1] + t[2]) + (t[3] + t[4])) + ((t[5] + t[6]) + (t[7] + t[8]));
   s[0] = float(m_t - rest);
 }
@@ -449,16 +491,17 @@ __device__ __forceinline__ void conserve(float (&s)[9], double m_t, double jx_t,
 // force (Fx, Fy) (FP64), then, for FP32 storage, conserve().
 template <typename S, bool MRT>
 __device__ __forceinline__ void update_node(typename Store<S>::R (&s)[9],
-                                            typename Store<S>::R drho, double rho64, double Fx,
-                                            double Fy, typename Store<S>::R ip2, const RunDev& d) {
+                                            typename Store<S>::R drho, typename Store<S>::P rho,
+                                            typename Store<S>::P Fx, typename Store<S>::P Fy,
+                                            typename Store<S>::R ip2, const RunDev& d) {
   using R = typename Store<S>::R;
   if constexpr (Store<S>::kConserve) {
     double m0, jx0, jy0;
     exact_moments(s, m0, jx0, jy0);
-    collide_any<MRT, R>(s, drho, R(rho64), mom_x(s), mom_y(s), R(Fx), R(Fy), ip2, d);
-    conserve(s, m0, jx0 + Fx, jy0 + Fy);
+    collide_any<MRT, R>(s, drho, R(rho), mom_x(s), mom_y(s), R(Fx), R(Fy), ip2, d);
+    conserve(s, m0, jx0 + double(Fx), jy0 + double(Fy));
   } else {
-    collide_any<MRT, R>(s, drho, R(rho64), mom_x(s), mom_y(s), R(Fx), R(Fy), ip2, d);
+    collide_any<MRT, R>(s, drho, R(rho), mom_x(s), mom_y(s), R(Fx), R(Fy), ip2, d);
   }
 }
 
@@ -473,10 +516,11 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
                                           const RunDev& d, int x0, int y0, int ncols, int nrows,
                                           unsigned long long step,
                                           unsigned long long* __restrict__ flag,
-                                          double (*ring)[64 * NW + 2], double* haloL,
-                                          double* haloR) {
+                                          typename Store<S>::P (*ring)[64 * NW + 2],
+                                          typename Store<S>::P* haloL, typename Store<S>::P* haloR) {
   using T = Store<S>;
   using R = typename T::R;
+  using P = typename T::P;
   constexpr int SW = 64 * NW;
   const int tid = threadIdx.x;
   LBM_TILE_CHECK(ncols >= 1 && ncols <= SW && nrows >= 1 && nrows <= LMAX && x0 >= 0 &&
@@ -486,7 +530,7 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
   const Cols cx = cols_of(act ? x : x0, d.nx);
   const int xl = x0 == 0 ? d.nx - 1 : x0 - 1;
   const int xr = x0 + ncols >= d.nx ? 0 : x0 + ncols;
-  const double rref = d.rho_ref;
+  const P rref = P(d.rho_ref);
   bool bad = false;
 
   // prologue: psi of the two halo columns for rows y0-1 .. y0+nrows
@@ -496,21 +540,21 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
     yy = yy < 0 ? yy + d.ny : (yy >= d.ny ? yy - d.ny : yy);
     R f[9];
     pull9<S>(src, d, cols_of((i & 1) ? xr : xl, d.nx), yy, f);
-    const double rho = rref + double(sum9(f));
-    ((i & 1) ? haloR : haloL)[k] = sqrt(psi2_of(rho, d));
+    const P rho = rref + P(sum9(f));
+    ((i & 1) ? haloR : haloL)[k] = psi_root(psi2_of(rho, d));
   }
 
   // preload rows y0-1 (ring slot 0) and y0 (slot 1); with PF = 2 also issue row y0+1
   R fc[9], fn[9];
-  double psi2c = 0.0;
+  P psi2c = P(0);
   if (act) {
     R f[9];
     pull9<S>(src, d, cx, y0 == 0 ? d.ny - 1 : y0 - 1, f);
     pull9<S>(src, d, cx, y0, fc);
     if (PF == 2) pull9<S>(src, d, cx, y0 + 1 == d.ny ? 0 : y0 + 1, fn);
-    ring[0][tid + 1] = sqrt(psi2_of(rref + double(sum9(f)), d));
-    psi2c = psi2_of(rref + double(sum9(fc)), d);
-    ring[1][tid + 1] = sqrt(psi2c);
+    ring[0][tid + 1] = psi_root(psi2_of(rref + P(sum9(f)), d));
+    psi2c = psi2_of(rref + P(sum9(fc)), d);
+    ring[1][tid + 1] = psi_root(psi2c);
   }
   __syncthreads();  // the halo columns are in LDS
   if (tid == 0) {
@@ -525,15 +569,15 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
     const int yn = y + 1 == d.ny ? 0 : y + 1;
     const int sl = (j + 2) & 3;
     R fnn[9];
-    double psi2n = 0.0;
+    P psi2n = P(0);
     if (act) {
       if (PF == 2) {
         if (j + 1 < nrows) pull9<S>(src, d, cx, yn + 1 == d.ny ? 0 : yn + 1, fnn);
       } else {
         pull9<S>(src, d, cx, yn, fn);
       }
-      psi2n = psi2_of(rref + double(sum9(fn)), d);
-      ring[sl][tid + 1] = sqrt(psi2n);
+      psi2n = psi2_of(rref + P(sum9(fn)), d);
+      ring[sl][tid + 1] = psi_root(psi2n);
     }
     if (tid == 0) {
       ring[sl][0] = haloL[j + 2];
@@ -541,13 +585,13 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
     }
     __syncthreads();
     if (act) {
-      double Fx, Fy;
-      force3x3(ring[j & 3], ring[(j + 1) & 3], ring[sl], tid + 1, d.mG, Fx, Fy);
+      P Fx, Fy;
+      force3x3(ring[j & 3], ring[(j + 1) & 3], ring[sl], tid + 1, P(d.mG), Fx, Fy);
       const R drho = sum9(fc);
-      const double rho64 = rref + double(drho);
-      bad |= !(psi2c > 0.0) || !(rho64 > 0.0);
+      const P rho = rref + P(drho);
+      bad |= !(psi2c > P(0)) || !(rho > P(0));
       const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
-      update_node<S, MRT>(fc, drho, rho64, Fx, Fy, ip2, d);
+      update_node<S, MRT>(fc, drho, rho, Fx, Fy, ip2, d);
       typename T::E* row = dst + (int64_t)y * d.rs;
 #pragma unroll
       for (int a = 0; a < 9; ++a)
@@ -602,8 +646,8 @@ __global__ __launch_bounds__(64 * NW) void k_step(const typename Store<S>::E* __
                                                   const unsigned long long* stepbase,
                                                   unsigned long long steplocal,
                                                   unsigned long long* flag) {
-  __shared__ double ring[4][64 * NW + 2];
-  __shared__ double haloL[LMAX + 2], haloR[LMAX + 2];
+  __shared__ typename Store<S>::P ring[4][64 * NW + 2];
+  __shared__ typename Store<S>::P haloL[LMAX + 2], haloR[LMAX + 2];
   constexpr int SW = 64 * NW;
   const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
   const bool frozen = *flag < step;  // diverged at an earlier step
@@ -675,10 +719,12 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
                                            const RunDev& d, int x0, int y0, int ncols, int nrows,
                                            unsigned long long step,
                                            unsigned long long* __restrict__ flag,
-                                           double (*ring1)[64 * NW], double (*ring2)[64 * NW],
+                                           typename Store<S>::P (*ring1)[64 * NW],
+                                           typename Store<S>::P (*ring2)[64 * NW],
                                            typename Store<S>::R (*xch)[64 * NW]) {
   using T = Store<S>;
   using R = typename T::R;
+  using P = typename T::P;
   const int tid = threadIdx.x;
   LBM_TILE_CHECK(ncols >= 1 && ncols <= 64 * NW - 6 && nrows >= 1 && x0 >= 0 &&
                  x0 + ncols <= d.nx && y0 >= 0 && y0 + nrows <= d.ny);
@@ -693,28 +739,28 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   auto wrapx = [&](int x) { return x < 0 ? x + d.nx : (x >= d.nx ? x - d.nx : x); };
   auto wrapy = [&](int y) { return y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y); };
   const Cols cx = cols_of(wrapx(x0 - 3 + min(tid, n0 - 1)), d.nx);
-  const double rref = d.rho_ref;
+  const P rref = P(d.rho_ref);
   bool bad1 = false, bad2 = false;
   const int ya = y0 - 3;                            // first psi(t) row
 
   // preload: psi(t) of rows y0-3 (ring slot 0) and y0-2 (slot 1); pulled row y0-2
   R fc[9] = {}, fn[9] = {};
-  double psi2c = 0.0;
+  P psi2c = P(0);
   if (act0) {
     R f[9];
     pull9<S>(src, d, cx, wrapy(ya), f);
     pull9<S>(src, d, cx, wrapy(ya + 1), fc);
     if (PF == 2) pull9<S>(src, d, cx, wrapy(ya + 2), fn);
-    ring1[0][tid] = sqrt(psi2_of(rref + double(sum9(f)), d));
-    psi2c = psi2_of(rref + double(sum9(fc)), d);
-    ring1[1][tid] = sqrt(psi2c);
+    ring1[0][tid] = psi_root(psi2_of(rref + P(sum9(f)), d));
+    psi2c = psi2_of(rref + P(sum9(fc)), d);
+    ring1[1][tid] = psi_root(psi2c);
   }
 
   // f*(t+1) of the last three step-one rows, kept for step two:
   // gA = row y1-1 (all 9), gB = row y1-2 (0,1,3,2,5,6), gC = row y1-3 (2,5,6)
   R gA[9] = {}, gB[6] = {}, gC[3] = {};
   R hp[9] = {};     // step-two pulled populations of the row collided next
-  double psi2p = 0.0;
+  P psi2p = P(0);
   const int n_one = nrows + 4;                      // step-one rows y0-2 .. y0+nrows+1
   // One row of the march.  Mode (SteadyMode) bit 16 marks a steady row, in
   // which every row condition below holds; bits 1, 2, 4, 8 make a phase run
@@ -728,7 +774,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
     const int y1 = y0 - 2 + j;                      // step-one row collided at this j
     // ---- phase 1: psi(t) of row y1+1; exchange of the rows step two pulls
     R fnn[9];
-    double psi2n = 0.0;
+    P psi2n = P(0);
     if ((St || j < n_one) && ((M & kRowPsi) || act0)) {
       // the row loads go out at raised wave priority, so a wave about to issue
       // them is not held behind the other wave's arithmetic (FP64: 1 % faster)
@@ -739,8 +785,8 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
         pull9<S>(src, d, cx, wrapy(y1 + 1), fn);
       }
       __builtin_amdgcn_s_setprio(0);
-      psi2n = psi2_of(rref + double(sum9(fn)), d);
-      ring1[(j + 2) & 3][tid] = sqrt(psi2n);
+      psi2n = psi2_of(rref + P(sum9(fn)), d);
+      ring1[(j + 2) & 3][tid] = psi_root(psi2n);
     }
     if ((St || j >= 3) && ((M & kRowPsi) || act1)) {  // step two pulls row q = y1 - 2 below
       xch[0][tid] = gB[1];
@@ -754,7 +800,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
     // ---- phase 2: step-two pull of row q = y1-2 and its psi(t+1); step-one collide of row y1
     const int q = y1 - 2;
     R hn[9];
-    double psi2q = 0.0;
+    P psi2q = P(0);
     if ((St || j >= 3) && ((M & kRowPull2) || pull2)) {
       hn[0] = gB[0];
       hn[1] = xch[0][tc - 1];
@@ -765,8 +811,8 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
       hn[6] = xch[3][tc + 1];
       hn[7] = xch[4][tc + 1];
       hn[8] = xch[5][tc - 1];
-      psi2q = psi2_of(rref + double(sum9(hn)), d);
-      ring2[(q - (y0 - 1)) & 3][tid] = sqrt(psi2q);
+      psi2q = psi2_of(rref + P(sum9(hn)), d);
+      ring2[(q - (y0 - 1)) & 3][tid] = psi_root(psi2q);
     }
     if (St || j >= 1) {  // rotate the kept step-one rows (gA was produced at j-1)
       gC[0] = gB[3]; gC[1] = gB[4]; gC[2] = gB[5];
@@ -775,14 +821,14 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
     }
     if ((St || j < n_one) && ((M & kRowCollide1) || act0)) {
       if ((M & kRowCollide1) || act1) {
-        double Fx, Fy;
-        force3x3(ring1[j & 3], ring1[(j + 1) & 3], ring1[(j + 2) & 3], tc, d.mG, Fx, Fy);
+        P Fx, Fy;
+        force3x3(ring1[j & 3], ring1[(j + 1) & 3], ring1[(j + 2) & 3], tc, P(d.mG), Fx, Fy);
         const R drho = sum9(fc);
-        const double rho64 = rref + double(drho);
+        const P rho = rref + P(drho);
         const bool chk = out && y1 >= y0 && y1 < y0 + nrows;
-        bad1 |= chk && (!(psi2c > 0.0) || !(rho64 > 0.0));
+        bad1 |= chk && (!(psi2c > P(0)) || !(rho > P(0)));
         const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
-        update_node<S, false>(fc, drho, rho64, Fx, Fy, ip2, d);
+        update_node<S, false>(fc, drho, rho, Fx, Fy, ip2, d);
 #pragma unroll
         for (int a = 0; a < 9; ++a) gA[a] = T::round(fc[a]);
       }
@@ -798,14 +844,14 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
     // ---- phase 3: step-two collide of row r = q-1 and store
     const int r = q - 1;
     if ((St || (j >= 4 && r >= y0 && r < y0 + nrows)) && ((M & kRowCollide2) || out)) {
-      double Fx, Fy;
+      P Fx, Fy;
       force3x3(ring2[(r - 1 - (y0 - 1)) & 3], ring2[(r - (y0 - 1)) & 3], ring2[(q - (y0 - 1)) & 3],
-               tc, d.mG, Fx, Fy);
+               tc, P(d.mG), Fx, Fy);
       const R drho = sum9(hp);
-      const double rho64 = rref + double(drho);
-      bad2 |= out && (!(psi2p > 0.0) || !(rho64 > 0.0));
+      const P rho = rref + P(drho);
+      bad2 |= out && (!(psi2p > P(0)) || !(rho > P(0)));
       const R ip2 = d.sig != 0.0 ? rcp(R(psi2p)) : R(0);
-      update_node<S, false>(hp, drho, rho64, Fx, Fy, ip2, d);
+      update_node<S, false>(hp, drho, rho, Fx, Fy, ip2, d);
       if (out) {
         typename T::E* orow = dst + (int64_t)wrapy(r) * d.rs;
 #pragma unroll
@@ -868,8 +914,8 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
                                                    unsigned long long steplocal,
                                                    unsigned long long* flag) {
   using R = typename Store<S>::R;
-  __shared__ double ring1[4][64 * NW];
-  __shared__ double ring2[4][64 * NW];
+  __shared__ typename Store<S>::P ring1[4][64 * NW];
+  __shared__ typename Store<S>::P ring2[4][64 * NW];
   __shared__ R xch[6][64 * NW];
   const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
   const bool frozen = *flag < step;  // diverged at an earlier step
@@ -922,8 +968,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step(const typename Store<S>:
                                                         const unsigned long long* stepbase,
                                                         unsigned long long steplocal,
                                                         unsigned long long* flags) {
-  __shared__ double ring[4][64 * NW + 2];
-  __shared__ double haloL[LMAX + 2], haloR[LMAX + 2];
+  __shared__ typename Store<S>::P ring[4][64 * NW + 2];
+  __shared__ typename Store<S>::P haloL[LMAX + 2], haloR[LMAX + 2];
   const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
   if (total > 0) {  // balanced schedule over whole-strip items
     balanced_pieces(items, nitems, total, xcd_remap(blockIdx.x, gridDim.x), LMAX,
@@ -964,8 +1010,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>
                                                          unsigned long long steplocal,
                                                          unsigned long long* flags) {
   using R = typename Store<S>::R;
-  __shared__ double ring1[4][64 * NW];
-  __shared__ double ring2[4][64 * NW];
+  __shared__ typename Store<S>::P ring1[4][64 * NW];
+  __shared__ typename Store<S>::P ring2[4][64 * NW];
   __shared__ R xch[6][64 * NW];
   const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
   if (total > 0) {  // balanced schedule over whole-strip items (no row cap: no per-row arrays)

@@ -127,6 +127,12 @@ RunDev make_rundev(const lbm_params& p, const EosConst& k, double rho_ref, int64
   d.wCe2 = 1.0 / 36.0 * d.Ce;
   d.wBe3_1 = 3.0 / 9.0 * d.Be;
   d.wBe3_2 = 3.0 / 36.0 * d.Be;
+  d.om_w0 = 4.0 / 9.0 * d.inv_tau;
+  d.om_w1 = 1.0 / 9.0 * d.inv_tau;
+  d.om_w2 = 1.0 / 36.0 * d.inv_tau;
+  d.om_3w1 = 3.0 / 9.0 * d.inv_tau;
+  d.om_3w2 = 3.0 / 36.0 * d.inv_tau;
+  d.om1 = 1.0 - d.inv_tau;
   d.rho_ref = rho_ref;
   d.run = run;
   d.mrt = 0;
@@ -359,6 +365,8 @@ hipError_t launch_batch2_s(const Tile& t, const void* src, void* dst, const RunD
                            const Item* items, int nitems, int total, const unsigned long long* base,
                            unsigned long long local, unsigned long long* flags, hipStream_t st) {
   switch (t.nw * 10 + t.pf) {
+    case 21: return launch_batch2_t<S, 2, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 22: return launch_batch2_t<S, 2, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
     case 41: return launch_batch2_t<S, 4, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
     case 42: return launch_batch2_t<S, 4, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
     case 81: return launch_batch2_t<S, 8, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
@@ -548,9 +556,15 @@ bool same_tile(const Tile& a, const Tile& b) {
 constexpr int kStepWaves[] = {1, 2, 4, 8, 16};
 constexpr int kBatchWaves[] = {1, 2, 4, 8};
 constexpr int kStep2Waves[] = {4, 8};  // two-step kernel: 250- and 506-column strips
+// The batched two-step kernel also has 2-wave blocks (122-column strips): the
+// lattices of a sweep are 64 to 512 columns wide, and a 250-column strip of a
+// narrow one leaves most lanes of its block idle.
+constexpr int kBatchStep2Waves[] = {2, 4, 8};
 
-bool valid_tile(int nw, int L, int pf, int maxnw, int ts = 1) {
-  if (ts == 2 && nw != 4 && nw != 8) return false;
+// A launch shape; ts2_min_nw is the smallest wave count of the two-step kernel
+// (2 for the batched launch, 4 for a single lattice).
+bool valid_tile(int nw, int L, int pf, int maxnw, int ts = 1, int ts2_min_nw = 4) {
+  if (ts == 2 && (nw < ts2_min_nw || (nw != 2 && nw != 4 && nw != 8))) return false;
   return (nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16) && nw <= maxnw && L >= 0 &&
          L <= LMAX && (pf == 1 || pf == 2) && (ts == 1 || ts == 2);
 }
@@ -1362,7 +1376,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
 }
 
 int lbm_batch_set_tile(lbm_batch* b, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
-  if (!b || !valid_tile(nw, L, depth, 8, steps) || (L > 0 && L < 4)) return LBM_EINVAL;
+  if (!b || !valid_tile(nw, L, depth, 8, steps, 2) || (L > 0 && L < 4)) return LBM_EINVAL;
   batch_drop_graphs(b);
   const int st = batch_items(b, Tile{nw, L, depth, steps});
   return st != LBM_OK ? st : batch_prepare_graphs(b);
@@ -1405,7 +1419,7 @@ int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth
     for (int pf : {1, 2})
       for (int L : {0, 4, 8, 16, 32, 64}) cand.push_back(Tile{nw, L, pf, 1});
   }
-  for (int nw : kStep2Waves) {
+  for (int nw : kBatchStep2Waves) {
     if (nw > 4 && 64 * (nw / 2) >= maxnx) continue;
     for (int pf : {1, 2})
       for (int L : {0, 32, 64}) cand.push_back(Tile{nw, L, pf, 2});

@@ -65,7 +65,7 @@ def test_batch_frozen_mrt_and_diagnostics_in_bounds(CL):
     c = th.maxwell_pr(0.6)
     gps.append(gp_bad)
     rhos.append(synth.droplet(96, 80, c.rho_l, c.rho_g, 20, 4.0, 0.005))
-    for tile in [(1, 4, 2), (4, 0, 2), (2, 8, 1), (4, 0, 2, 2), (8, 32, 1, 2)]:
+    for tile in [(1, 4, 2), (4, 0, 2), (2, 8, 1), (4, 0, 2, 2), (8, 32, 1, 2), (2, 0, 2, 2)]:
         b = L.Batch(gps, rhos)
         b.set_tile(*tile)
         b.set_graph_steps(10)

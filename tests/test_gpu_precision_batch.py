@@ -139,7 +139,7 @@ def _batch_runs(L, prec=0):
 
 
 @pytest.mark.parametrize("tile", [(1, 16, 2), (2, 0, 1), (4, 8, 2), (8, 0, 2), (4, 0, 2, 2), (8, 32, 1, 2),
-                                  (4, 32, 2, 2)])
+                                  (4, 32, 2, 2), (2, 0, 2, 2), (2, 32, 1, 2)])
 def test_batch_equals_single_runs_bitwise(L, tile):
     gps, _, rhos = _batch_runs(L)
     b = L.Batch(gps, rhos)
@@ -195,7 +195,8 @@ def test_batch_divergence_is_isolated(L):
     b.close()
 
 
-@pytest.mark.parametrize("tile,k", [((2, 8, 1), 12), ((4, 0, 2, 2), 12), ((4, 32, 1, 2), 10)])
+@pytest.mark.parametrize("tile,k", [((2, 8, 1), 12), ((4, 0, 2, 2), 12), ((4, 32, 1, 2), 10),
+                                    ((2, 0, 2, 2), 10)])
 def test_batch_graph_bitwise(L, tile, k):
     # graph replays (for two steps per launch: k/2 launches, odd for k = 10) against eager
     # single steps, FP32 deviations
