@@ -209,11 +209,11 @@ def main():
         "dtype": PREC_NAME[args.precision],
         "data": "synthetic",
         "config": dict(cfg, precision=PREC_NAME[args.precision], tile=res["tile"],
-                       graph_steps=args.graph_steps, settle_ms=args.settle_ms),
+                       graph_steps=res["graph_steps"], settle_ms=args.settle_ms),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_for(args.workload, args.precision, res["tile"]),
-                     "kernel": "k_step2" if ts == 2 else "k_step", "steps_per_launch": ts,
+                     "kernel": {1: "k_step", 2: "k_step2", 3: "k_step3"}[ts], "steps_per_launch": ts,
                      "bytes_per_lup": bpl / ts, "kernel_avg_us": round(launch_ms * 1e3, 2),
                      # MLUPS x the single-step 144 B/LUP over the peak (exceeds 1 only
                      # when steps are fused; not a bandwidth)
@@ -233,6 +233,17 @@ def main():
                                                  "frac": round(gbs / PEAK_HBM_GBS, 4),
                                                  "bytes_per_lup": BYTES_PER_LUP[prec] / r["tile"][3]}
             log(f"precision {PREC_NAME[prec]}: {r['mlups']:.0f} MLUPS")
+        # the FP64 two-step kernel on the same workload, for its own roofline
+        # fraction when the tuner has picked the three-step one
+        r = time_lattice(lbm, torch, nx, ny, rho0, kw, 0, args.steps, args.warmup, args.graph_steps,
+                         False, (4, 0, 2, 2), settle_ms=args.settle_ms)
+        gbs = BYTES_PER_LUP[0] * nx * ny / (r["kernel_ms"] * 2 * 1e-3) / 1e9
+        out["precision"]["f64_two_step"] = {"mlups": round(r["mlups"], 1), "tile": r["tile"],
+                                            "kernel_avg_us": round(r["kernel_ms"] * 2e3, 2),
+                                            "achieved_gbs": round(gbs, 1),
+                                            "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                            "traffic": traffic_for(args.workload, 0, r["tile"])}
+        log(f"f64 two-step: {r['mlups']:.0f} MLUPS")
     if "droplet1024" in legs and args.workload != "droplet1024":
         d = {}
         for t in (0.6, 0.8):
@@ -304,22 +315,30 @@ def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_s
     elif tune:
         lat.tune()
     tile = list(lat.get_tile())
-    if graph_steps:
-        lat.set_graph_steps(graph_steps)   # captures and uploads the graphs of both parities now
+    ts = tile[3]
+    # a graph holds whole launches of the tile: its length is rounded down to a
+    # multiple of the tile's steps (and of 2)
+    g = graph_steps - graph_steps % (6 if ts == 3 else 2) if graph_steps else 0
+    if g:
+        lat.set_graph_steps(g)   # captures and uploads the graphs of both parities now
     settle(lat, torch, settle_ms)
     lat.step(warmup)
     st, _, div = lat.status()
     if st != lbm.LBM_OK:
         lat.close()
         raise Diverged(div)
+    # the kernel average is taken over the whole launches of the tile; a
+    # remainder of fewer steps (one shorter launch) is timed after them
+    n_main = steps - steps % ts
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     captures = lat.graph_captures()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(lat.stream)
-    lat.step(steps)
+    lat.step(n_main)
     e1.record(lat.stream)
+    lat.step(steps - n_main)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if lat.graph_captures() != captures:
@@ -329,7 +348,7 @@ def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_s
     if st != lbm.LBM_OK:
         raise Diverged(div)
     return {"mlups": nx * ny * steps / wall / 1e6, "wall_s": wall,
-            "kernel_ms": e0.elapsed_time(e1) / steps, "tile": tile}
+            "kernel_ms": e0.elapsed_time(e1) / max(n_main, 1), "tile": tile, "graph_steps": g}
 
 
 def traffic_for(workload, precision, tile):

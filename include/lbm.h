@@ -213,12 +213,15 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes);
  * `rows` rows; rows = 0 selects the balanced schedule, in which a grid sized
  * to the GPU's resident capacity splits all strip rows evenly.  `depth` (1 or
  * 2) is how many rows of loads are in flight while a row is collided.
- * `steps` (1 or 2) is the number of time steps one launch advances: with 2,
- * the populations of the intermediate step stay on chip (registers and LDS),
- * so they cross HBM once per two steps; its strips are at most
+ * `steps` (1, 2 or 3) is the number of time steps one launch advances: with
+ * 2, the populations of the intermediate step stay on chip (registers and
+ * LDS), so they cross HBM once per two steps; its strips are at most
  * 64*waves - 6 columns wide (the six extra columns are recomputed), spread
- * evenly over nx (FP64: strip edges on 64-byte boundaries), waves in {4, 8},
- * and an odd remainder of lbm_step(n) runs one single step.
+ * evenly over nx (FP64: strip edges on 64-byte boundaries), waves in {4, 8}.
+ * With 3 (FP64 and FP32-storage-FP64-collision lattices of at least 5 x 5;
+ * waves 4 or 8, depth 1; else LBM_ENOTSUP or LBM_EINVAL) they cross HBM once per
+ * three steps, strips at most 64*waves - 10 columns wide.  A remainder of
+ * lbm_step(n) smaller than `steps` runs as one launch of that many steps.
  * waves in {1, 2, 4, 8, 16}; rows in [0, 128].  lbm_tune times the candidates
  * on the current state without advancing it and keeps the fastest per lattice
  * step; the choice is cached per (nx, ny, precision) for the life of the
@@ -228,7 +231,8 @@ int lbm_set_tile(lbm_ctx* c, int32_t waves, int32_t rows, int32_t depth, int32_t
 int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
 
 /* Replay n steps through captured HIP graphs of k steps each (k even, >= 2;
- * 0 disables).  Needs a non-null stream.  The graphs of both buffer parities
+ * 0 disables; a graph holds k / steps launches of the tile and one launch for
+ * a remainder).  Needs a non-null stream.  The graphs of both buffer parities
  * are captured, instantiated and uploaded by this call (and again by
  * lbm_set_tile / lbm_tune when the tile changes), so lbm_step only replays
  * them; synchronous.  Results are bitwise identical to eager launches. */
@@ -244,8 +248,8 @@ int lbm_set_graph_steps(lbm_ctx* c, int32_t k);
  * c_s^2 (1/s_e - 1/2).  Each moment gets Eq. (31)'s forcing moment with
  * v' = v + sigma F / ((1/s - 1/2) psi^2) for its own rate s, so rates all equal
  * to 1/tau give the BGK improved scheme.  Improved scheme only, FP64 or FP32
- * deviation storage (else LBM_ENOTSUP); one time step per launch (a two-step
- * tile becomes the same tile with one step; lbm_set_tile with steps = 2 then
+ * deviation storage (else LBM_ENOTSUP); one time step per launch (a multi-step
+ * tile becomes the same tile with one step; lbm_set_tile with steps > 1 then
  * returns LBM_ENOTSUP).  Captured graphs are rebuilt. */
 int lbm_set_mrt(lbm_ctx* c, const double* rates);
 

@@ -957,6 +957,280 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
   }
 }
 
+// ---- three time steps per launch ----------------------------------------------
+
+// Three steps per launch: the pipeline of tile_step2 with a third level.  Lane
+// i of a block owns column c = x0 - 5 + i for all three steps, i < ncols + 10:
+//   * every lane pulls its column and evaluates psi(t);
+//   * lanes 1 .. ncols+8 run step one and keep f*(t+1) (the last three rows);
+//   * lanes 2 .. ncols+7 pull f*(t+1) and evaluate psi(t+1), lanes 3 ..
+//     ncols+6 run step two and keep f*(t+2) likewise;
+//   * lanes 4 .. ncols+5 pull f*(t+2) and evaluate psi(t+2), lanes 5 ..
+//     ncols+4 run step three and write the columns [x0, x0+ncols).
+// Rows: step three writes [y0, y0+nrows), so step two produces rows y0-2 ..
+// y0+nrows+1, step one rows y0-4 .. y0+nrows+3, and psi(t) is evaluated on
+// rows y0-5 .. y0+nrows+4.  At march row j step one collides y1 = y0-4+j,
+// step two pulls y1-2 and collides y1-3, step three pulls y1-5 and collides
+// y1-6.  Each step pulls the x-unshifted directions of the previous step's
+// rows from the lane's own registers and the six shifted ones through an LDS
+// exchange row, as in tile_step2; two barriers per march row.  Same
+// arithmetic in the same order as three single-step launches: bitwise equal.
+template <typename S, int NW>
+__device__ __forceinline__ void tile_step3(const typename Store<S>::E* __restrict__ src,
+                                           typename Store<S>::E* __restrict__ dst,
+                                           const RunDev& d, int x0, int y0, int ncols, int nrows,
+                                           unsigned long long step,
+                                           unsigned long long* __restrict__ flag,
+                                           typename Store<S>::P (*ring1)[64 * NW],
+                                           typename Store<S>::P (*ring2)[64 * NW],
+                                           typename Store<S>::P (*ring3)[64 * NW],
+                                           typename Store<S>::R (*xch1)[64 * NW],
+                                           typename Store<S>::R (*xch2)[64 * NW]) {
+  using T = Store<S>;
+  using R = typename T::R;
+  using P = typename T::P;
+  const int tid = threadIdx.x;
+  LBM_TILE_CHECK(ncols >= 1 && ncols <= 64 * NW - 10 && nrows >= 1 && x0 >= 0 &&
+                 x0 + ncols <= d.nx && y0 >= 0 && y0 + nrows <= d.ny);
+  const int n0 = ncols + 10;                        // lanes that evaluate psi(t)
+  const bool act0 = tid < n0;
+  const bool act1 = tid >= 1 && tid < n0 - 1;       // step one
+  const bool pull2 = tid >= 2 && tid < n0 - 2;      // step-two pull, psi(t+1)
+  const bool act2 = tid >= 3 && tid < n0 - 3;       // step two
+  const bool pull3 = tid >= 4 && tid < n0 - 4;      // step-three pull, psi(t+2)
+  const bool out = tid >= 5 && tid < n0 - 5;        // step three and the store
+  const int tc = min(max(tid, 1), 64 * NW - 2);     // LDS neighbour index inside the rows
+  auto wrapx = [&](int x) { return x < 0 ? x + d.nx : (x >= d.nx ? x - d.nx : x); };
+  auto wrapy = [&](int y) { return y < 0 ? y + d.ny : (y >= d.ny ? y - d.ny : y); };
+  const Cols cx = cols_of(wrapx(x0 - 5 + min(tid, n0 - 1)), d.nx);
+  const P rref = P(d.rho_ref);
+  bool bad1 = false, bad2 = false, bad3 = false;
+  const int ya = y0 - 5;                            // first psi(t) row (ring1 slot 0)
+  const int yb = y0 - 3;                            // first psi(t+1) row (ring2 slot 0)
+  const int yc = y0 - 1;                            // first psi(t+2) row (ring3 slot 0)
+
+  R fc[9] = {}, fn[9] = {};
+  P psi2c = P(0);
+  if (act0) {
+    R f[9];
+    pull9<S>(src, d, cx, wrapy(ya), f);
+    pull9<S>(src, d, cx, wrapy(ya + 1), fc);
+    ring1[0][tid] = psi_root(psi2_of(rref + P(sum9(f)), d));
+    psi2c = psi2_of(rref + P(sum9(fc)), d);
+    ring1[1][tid] = psi_root(psi2c);
+  }
+  // f*(t+1) kept for step two: gA = row y1-1 (all 9), gB = y1-2 (0,1,3,2,5,6),
+  // gC = y1-3 (2,5,6); f*(t+2) kept for step three likewise (kA, kB, kC, rows
+  // produced one, two and three march rows ago)
+  R gA[9] = {}, gB[6] = {}, gC[3] = {};
+  R kA[9] = {}, kB[6] = {}, kC[3] = {};
+  R hp[9] = {}, hp3[9] = {};   // pulled rows of steps two and three collided next
+  P psi2p = P(0), psi3p = P(0);
+  const int n_one = nrows + 8;                      // step-one rows y0-4 .. y0+nrows+3
+  auto row = [&](const int j, auto steady) __attribute__((always_inline)) {
+    constexpr bool St = decltype(steady)::value;
+    const int y1 = y0 - 4 + j;
+    // ---- phase 1: psi(t) of row y1+1; exchange rows for steps two and three
+    P psi2n = P(0);
+    if ((St || j < n_one) && act0) {
+      __builtin_amdgcn_s_setprio(2);
+      pull9<S>(src, d, cx, wrapy(y1 + 1), fn);
+      __builtin_amdgcn_s_setprio(0);
+      psi2n = psi2_of(rref + P(sum9(fn)), d);
+      ring1[(j + 2) & 3][tid] = psi_root(psi2n);
+    }
+    const bool lv2 = St || (j >= 3 && j <= n_one);  // step two pulls q2 = y1-2
+    const bool lv3 = St || j >= 8;                  // step three pulls q3 = y1-5
+    // In steady rows the exchange writes and the pulls of steps two and three
+    // run on every lane: a lane outside a range writes and reads only LDS slots
+    // that no lane inside the range reads (tc keeps its neighbour reads inside
+    // the rows), so its values are never used.
+    if (lv2 && (St || act1)) {
+      xch1[0][tid] = gB[1];
+      xch1[1][tid] = gB[2];
+      xch1[2][tid] = gC[1];
+      xch1[3][tid] = gC[2];
+      xch1[4][tid] = gA[7];
+      xch1[5][tid] = gA[8];
+    }
+    if (lv3 && (St || act2)) {
+      xch2[0][tid] = kB[1];
+      xch2[1][tid] = kB[2];
+      xch2[2][tid] = kC[1];
+      xch2[3][tid] = kC[2];
+      xch2[4][tid] = kA[7];
+      xch2[5][tid] = kA[8];
+    }
+    __syncthreads();
+    // ---- phase 2: pulls of steps two and three and their psi; step-one collide
+    const int q2 = y1 - 2, q3 = y1 - 5;
+    R hn[9], hn3[9];
+    P psi2q = P(0), psi3q = P(0);
+    if (lv2 && (St || pull2)) {
+      hn[0] = gB[0];
+      hn[1] = xch1[0][tc - 1];
+      hn[2] = gC[0];
+      hn[3] = xch1[1][tc + 1];
+      hn[4] = gA[4];
+      hn[5] = xch1[2][tc - 1];
+      hn[6] = xch1[3][tc + 1];
+      hn[7] = xch1[4][tc + 1];
+      hn[8] = xch1[5][tc - 1];
+      psi2q = psi2_of(rref + P(sum9(hn)), d);
+      ring2[(q2 - yb) & 3][tid] = psi_root(psi2q);
+    }
+    if (lv3 && (St || pull3)) {
+      hn3[0] = kB[0];
+      hn3[1] = xch2[0][tc - 1];
+      hn3[2] = kC[0];
+      hn3[3] = xch2[1][tc + 1];
+      hn3[4] = kA[4];
+      hn3[5] = xch2[2][tc - 1];
+      hn3[6] = xch2[3][tc + 1];
+      hn3[7] = xch2[4][tc + 1];
+      hn3[8] = xch2[5][tc - 1];
+      psi3q = psi2_of(rref + P(sum9(hn3)), d);
+      ring3[(q3 - yc) & 3][tid] = psi_root(psi3q);
+    }
+    if (St || j >= 1) {  // rotate the kept step-one rows (gA was produced at j-1)
+      gC[0] = gB[3]; gC[1] = gB[4]; gC[2] = gB[5];
+      gB[0] = gA[0]; gB[1] = gA[1]; gB[2] = gA[3];
+      gB[3] = gA[2]; gB[4] = gA[5]; gB[5] = gA[6];
+    }
+    if ((St || j < n_one) && act0) {
+      if (act1) {
+        P Fx, Fy;
+        force3x3(ring1[j & 3], ring1[(j + 1) & 3], ring1[(j + 2) & 3], tc, P(d.mG), Fx, Fy);
+        const R drho = sum9(fc);
+        const P rho = rref + P(drho);
+        const bool chk = out && y1 >= y0 && y1 < y0 + nrows;
+        bad1 |= chk && (!(psi2c > P(0)) || !(rho > P(0)));
+        const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
+        update_node<S, false>(fc, drho, rho, Fx, Fy, ip2, d);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) gA[a] = T::round(fc[a]);
+      }
+#pragma unroll
+      for (int a = 0; a < 9; ++a) fc[a] = fn[a];
+      psi2c = psi2n;
+    }
+    __syncthreads();
+    // ---- phase 3: step-two collide of row r2 = q2-1; step-three collide of r3 = q3-1 and store
+    const int r2 = q2 - 1, r3 = q3 - 1;
+    if (St || (j >= 5 && j <= n_one)) {
+      // rotate the kept step-two rows (kA was produced at j-1)
+      kC[0] = kB[3]; kC[1] = kB[4]; kC[2] = kB[5];
+      kB[0] = kA[0]; kB[1] = kA[1]; kB[2] = kA[3];
+      kB[3] = kA[2]; kB[4] = kA[5]; kB[5] = kA[6];
+      if (act2) {
+        P Fx, Fy;
+        force3x3(ring2[(r2 - 1 - yb) & 3], ring2[(r2 - yb) & 3], ring2[(q2 - yb) & 3], tc, P(d.mG),
+                 Fx, Fy);
+        const R drho = sum9(hp);
+        const P rho = rref + P(drho);
+        const bool chk = out && r2 >= y0 && r2 < y0 + nrows;
+        bad2 |= chk && (!(psi2p > P(0)) || !(rho > P(0)));
+        const R ip2 = d.sig != 0.0 ? rcp(R(psi2p)) : R(0);
+        update_node<S, false>(hp, drho, rho, Fx, Fy, ip2, d);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) kA[a] = T::round(hp[a]);
+      }
+    }
+    if (lv2) {
+#pragma unroll
+      for (int a = 0; a < 9; ++a) hp[a] = hn[a];
+      psi2p = psi2q;
+    }
+    if ((St || j >= 10) && out) {
+      P Fx, Fy;
+      force3x3(ring3[(r3 - 1 - yc) & 3], ring3[(r3 - yc) & 3], ring3[(q3 - yc) & 3], tc, P(d.mG),
+               Fx, Fy);
+      const R drho = sum9(hp3);
+      const P rho = rref + P(drho);
+      bad3 |= !(psi3p > P(0)) || !(rho > P(0));
+      const R ip2 = d.sig != 0.0 ? rcp(R(psi3p)) : R(0);
+      update_node<S, false>(hp3, drho, rho, Fx, Fy, ip2, d);
+      typename T::E* orow = dst + (int64_t)wrapy(r3) * d.rs;
+#pragma unroll
+      for (int a = 0; a < 9; ++a)
+        if (index_ok(orow + a * d.plane + cx.x - dst, d.elems)) T::st(orow + a * d.plane + cx.x, hp3[a]);
+    }
+    if (lv3) {
+#pragma unroll
+      for (int a = 0; a < 9; ++a) hp3[a] = hn3[a];
+      psi3p = psi3q;
+    }
+  };
+  // rows 0..9 fill the pipeline, 10 .. n_one-1 are steady (every row condition
+  // above holds), the last two drain it
+  using Edge = std::integral_constant<bool, false>;
+  using Steady = std::integral_constant<bool, true>;
+  for (int j = 0; j < 10; ++j) row(j, Edge{});
+  for (int j = 10; j < n_one; ++j) row(j, Steady{});
+  for (int j = max(10, n_one); j < n_one + 2; ++j) row(j, Edge{});
+  const auto b1 = __ballot(bad1), b2 = __ballot(bad2), b3 = __ballot(bad3);
+  if (__lane_id() == 0 && (b1 | b2 | b3) != 0)
+    atomicMin(flag, b1 != 0 ? step : (b2 != 0 ? step + 1 : step + 2));
+}
+
+// Three steps per launch over the single lattice (FP64 collision arithmetic):
+// strips of at most 64*NW - 10 columns spread evenly over nx, edges aligned as
+// for the two-step kernel; L > 0: one block per (strip, L-row chunk); L == 0:
+// the balanced schedule of k_step2.
+template <typename S, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_step3(const typename Store<S>::E* __restrict__ src,
+                                                   typename Store<S>::E* __restrict__ dst,
+                                                   RunDev d, int L, int nstrips,
+                                                   const unsigned long long* stepbase,
+                                                   unsigned long long steplocal,
+                                                   unsigned long long* flag) {
+  using R = typename Store<S>::R;
+  using P = typename Store<S>::P;
+  __shared__ P ring1[4][64 * NW];
+  __shared__ P ring2[4][64 * NW];
+  __shared__ P ring3[4][64 * NW];
+  __shared__ R xch1[6][64 * NW];
+  __shared__ R xch2[6][64 * NW];
+  const unsigned long long step = (stepbase ? *stepbase : 0ull) + steplocal;
+  const bool frozen = *flag < step;  // diverged at an earlier step
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  auto strip = [&](int sx, int& x0, int& nc) {
+    constexpr int A = Step2Align<S>::value;
+    auto edge = [&](int k) {
+      return k >= nstrips ? d.nx : (int)((int64_t)k * d.nx / nstrips) / A * A;
+    };
+    x0 = edge(sx);
+    nc = edge(sx + 1) - x0;
+  };
+  if (L > 0) {
+    const int sy = t / nstrips, sx = t - sy * nstrips;
+    int x0, nc;
+    strip(sx, x0, nc);
+    const int y0 = sy * L;
+    if (frozen)
+      copy_tile<S, 64 * NW>(src, dst, d, x0, y0, nc, min(L, d.ny - y0));
+    else
+      tile_step3<S, NW>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2, ring3,
+                        xch1, xch2);
+    return;
+  }
+  const int64_t total = (int64_t)nstrips * d.ny;
+  int64_t r = total * t / gridDim.x;
+  const int64_t e = total * (t + 1) / gridDim.x;
+  while (r < e) {
+    const int s = (int)(r / d.ny), y = (int)(r - (int64_t)s * d.ny);
+    const int n = (int)min(e - r, (int64_t)(d.ny - y));
+    int x0, nc;
+    strip(s, x0, nc);
+    if (frozen)
+      copy_tile<S, 64 * NW>(src, dst, d, x0, y, nc, n);
+    else
+      tile_step3<S, NW>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, ring3, xch1, xch2);
+    r += n;
+    __syncthreads();  // LDS is reused by the next piece
+  }
+}
+
 // Persistent batched step: blocks of XCD k walk the k-th contiguous eighth of
 // the work list.  Grid must be a multiple of 8.
 template <typename S, int NW, int PF, bool MRT = false>

@@ -289,10 +289,46 @@ hipError_t launch_step2_s(const Tile& t, const void* src, void* dst, const RunDe
   }
 }
 
-// One launch of the tile: t.ts time steps (1 or 2) from src into dst.
+template <typename S, int NW>
+hipError_t launch_step3_t(const void* src, void* dst, const RunDev& d, int L,
+                          const unsigned long long* base, unsigned long long local,
+                          unsigned long long* flag, hipStream_t st) {
+  const int SW = 64 * NW;
+  // strips of at most SW - 10 columns after their edges are aligned down to A columns
+  constexpr int A = Step2Align<S>::value;
+  const int nstrips = (d.nx + SW - 11 - (A - 1)) / (SW - 10 - (A - 1));
+  int grid;
+  if (L > 0) {
+    grid = nstrips * ((d.ny + L - 1) / L);
+  } else {
+    const int64_t rows = (int64_t)nstrips * d.ny;
+    grid = resident_blocks((const void*)k_step3<S, NW>, SW);
+    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, rows / 8));
+  }
+  using E = typename Store<S>::E;
+  hipLaunchKernelGGL((k_step3<S, NW>), dim3(grid), dim3(SW), 0, st, static_cast<const E*>(src),
+                     static_cast<E*>(dst), d, L, nstrips, base, local, flag);
+  return hipGetLastError();
+}
+
+// Storage types with a three-step kernel: those with FP64 collision arithmetic
+// (the FP32 and FP16 arithmetic paths are bound by instruction issue, where
+// the recomputed halo of a third step costs more than the traffic it saves).
+bool has_step3(int prec) { return prec == LBM_PREC_F64 || prec == LBM_PREC_F32DEV_F64; }
+
+// One launch of the tile: t.ts time steps (1, 2 or 3) from src into dst.
 hipError_t launch_step(int prec, const Tile& t, const void* src, void* dst, const RunDev& d,
                        const unsigned long long* base, unsigned long long local,
                        unsigned long long* flag, hipStream_t st) {
+  if (t.ts == 3) {
+    if (prec == LBM_PREC_F64)
+      return t.nw == 8 ? launch_step3_t<double, 8>(src, dst, d, t.L, base, local, flag, st)
+                       : launch_step3_t<double, 4>(src, dst, d, t.L, base, local, flag, st);
+    if (prec == LBM_PREC_F32DEV_F64)
+      return t.nw == 8 ? launch_step3_t<f32s_f64a, 8>(src, dst, d, t.L, base, local, flag, st)
+                       : launch_step3_t<f32s_f64a, 4>(src, dst, d, t.L, base, local, flag, st);
+    return hipErrorInvalidValue;
+  }
   if (t.ts == 2) {
     if (prec == LBM_PREC_F64) return launch_step2_s<double>(t, src, dst, d, base, local, flag, st);
     if (prec == LBM_PREC_F32DEV) return launch_step2_s<float>(t, src, dst, d, base, local, flag, st);
@@ -563,11 +599,25 @@ constexpr int kBatchStep2Waves[] = {2, 4, 8};
 
 // A launch shape; ts2_min_nw is the smallest wave count of the two-step kernel
 // (2 for the batched launch, 4 for a single lattice).
+// The three-step kernel (single lattice only) has 4- and 8-wave blocks and
+// row prefetch depth 1.
 bool valid_tile(int nw, int L, int pf, int maxnw, int ts = 1, int ts2_min_nw = 4) {
   if (ts == 2 && (nw < ts2_min_nw || (nw != 2 && nw != 4 && nw != 8))) return false;
+  if (ts == 3 && (ts2_min_nw != 4 || (nw != 4 && nw != 8) || pf != 1)) return false;
   return (nw == 1 || nw == 2 || nw == 4 || nw == 8 || nw == 16) && nw <= maxnw && L >= 0 &&
-         L <= LMAX && (pf == 1 || pf == 2) && (ts == 1 || ts == 2);
+         L <= LMAX && (pf == 1 || pf == 2) && ts >= 1 && ts <= 3;
 }
+
+// A remainder of r < t.ts steps of a multi-step tile: one launch of r steps
+// (the two-step kernel for two, with the same waves, rows and depth, which
+// every three-step tile also suits).
+Tile remainder_tile(Tile t, int r) {
+  t.ts = r;
+  return t;
+}
+
+// Launches in a graph of k steps: k / ts full launches and one for the remainder.
+int graph_launches(int k, int ts) { return k / ts + (k % ts != 0 ? 1 : 0); }
 
 void drop_graphs(lbm_ctx* c) {
   for (int i = 0; i < 2; ++i)
@@ -592,10 +642,11 @@ int capture_graph(lbm_ctx* c, int parity) {
   hipGraph_t g;
   HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  const int launches = c->graph_k / c->tile.ts;  // graph_k is even
-  for (int i = 0; i < launches && e == hipSuccess; ++i) {
+  const int full = c->graph_k / c->tile.ts, rest = c->graph_k % c->tile.ts;
+  for (int i = 0; i < graph_launches(c->graph_k, c->tile.ts) && e == hipSuccess; ++i) {
     const int s = (parity + i) & 1;
-    e = launch_step(c->p.precision, c->tile, c->buf[s], c->buf[s ^ 1], c->d, c->ctr,
+    const Tile t = i < full ? c->tile : remainder_tile(c->tile, rest);
+    e = launch_step(c->p.precision, t, c->buf[s], c->buf[s ^ 1], c->d, c->ctr,
                     (unsigned long long)i * c->tile.ts, c->flag, c->st);
   }
   if (e == hipSuccess) {
@@ -653,6 +704,42 @@ float time_launches(hipStream_t st, Launch&& launch, int reps) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return e == hipSuccess ? ms : -1.f;
+}
+
+// Pick the fastest tile per lattice step.  time_one(t) times launches of one
+// candidate (ms per lattice step; negative on a HIP error; +inf to skip it).
+// A single pass in candidate order is biased by the GPU's clocks drifting
+// down over a long back-to-back run (a kernel trace of the FP64 4096 x 4096
+// tune shows candidates late in the list running up to 40 % slower than the
+// same kernels before or after the tune), so the best kRefine of the first
+// pass are timed again in kRefineRounds rotated rounds and ranked by their
+// best time.  Returns LBM_OK or LBM_EHIP.
+template <class TimeOne>
+int pick_tile(const std::vector<Tile>& cand, TimeOne&& time_one, Tile& best_tile) {
+  constexpr int kRefine = 6, kRefineRounds = 3;
+  std::vector<std::pair<float, int>> first;
+  for (int i = 0; i < (int)cand.size(); ++i) {
+    const float ms = time_one(cand[i]);
+    if (ms < 0) return LBM_EHIP;
+    if (ms < 1e30f) first.push_back({ms, i});
+  }
+  if (first.empty()) return LBM_OK;
+  std::sort(first.begin(), first.end());
+  const int n = std::min<int>(kRefine, (int)first.size());
+  std::vector<float> best(n);
+  for (int k = 0; k < n; ++k) best[k] = first[k].first;
+  for (int r = 0; r < kRefineRounds; ++r)
+    for (int q = 0; q < n; ++q) {
+      const int k = (q + r) % n;
+      const float ms = time_one(cand[first[k].second]);
+      if (ms < 0) return LBM_EHIP;
+      best[k] = std::min(best[k], ms);
+    }
+  int kb = 0;
+  for (int k = 1; k < n; ++k)
+    if (best[k] < best[kb]) kb = k;
+  best_tile = cand[first[kb].second];
+  return LBM_OK;
 }
 
 }  // namespace
@@ -766,13 +853,13 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       HIPCHK(hipGraphLaunch(c->gexec[c->cur], c->st));
       done += c->graph_k;
       c->step += c->graph_k;
-      c->cur ^= (c->graph_k / c->tile.ts) & 1;  // one buffer swap per launch
+      c->cur ^= graph_launches(c->graph_k, c->tile.ts) & 1;  // one buffer swap per launch
     }
   }
   while (done < n) {
     const int s = c->cur;
     Tile t = c->tile;
-    if (n - done < t.ts) t.ts = 1;  // odd remainder of a two-step tile: one single step
+    if (n - done < t.ts) t = remainder_tile(t, (int)(n - done));  // fewer steps than the tile's
     HIPCHK(launch_step(c->p.precision, t, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
                        (unsigned long long)c->step, c->flag, c->st));
     c->cur ^= 1;
@@ -960,6 +1047,8 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
 int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
   if (!c || !valid_tile(nw, L, depth, 16, steps)) return LBM_EINVAL;
   if (c->d.mrt && steps != 1) return LBM_ENOTSUP;
+  if (steps == 3 && !has_step3(c->p.precision)) return LBM_ENOTSUP;
+  if (steps == 3 && (c->p.nx < 5 || c->p.ny < 5)) return LBM_EINVAL;  // halo of 5 wraps once
   c->tile = Tile{nw, L, depth, steps};
   return prepare_graphs(c);
 }
@@ -975,7 +1064,6 @@ int lbm_get_tile(lbm_ctx* c, int32_t* nw, int32_t* L, int32_t* depth, int32_t* s
 
 int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, int32_t* steps_out) {
   if (!c) return LBM_EINVAL;
-  float best = 1e30f;
   Tile bt = c->tile;
   const int s = c->cur;
   const int64_t nodes = (int64_t)c->p.nx * c->p.ny;
@@ -994,20 +1082,26 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, in
       for (int L : {0, 32, 64, 128})
         if (L <= 2 * c->p.ny) cand.push_back(Tile{nw, L, pf, 2});
   }
-  for (const Tile& t : cand) {
-    const float ms = time_launches(
-        c->st,
-        [&] {
-          return launch_step(c->p.precision, t, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
-                             (unsigned long long)c->step, c->flag, c->st);
-        },
-        reps);
-    if (ms < 0) return LBM_EHIP;
-    if (ms / t.ts < best) {  // time per lattice step
-      best = ms / t.ts;
-      bt = t;
+  if (!c->d.mrt && has_step3(c->p.precision) && c->p.nx >= 16 && c->p.ny >= 16)
+    for (int nw : {4, 8}) {
+      if (nw > 4 && 64 * (nw / 2) >= c->p.nx) continue;
+      for (int L : {0, 64, 128})
+        if (L <= 2 * c->p.ny) cand.push_back(Tile{nw, L, 1, 3});
     }
-  }
+  const int pst = pick_tile(
+      cand,
+      [&](const Tile& t) {
+        const float ms = time_launches(
+            c->st,
+            [&] {
+              return launch_step(c->p.precision, t, c->buf[s], c->buf[s ^ 1], c->d, nullptr,
+                                 (unsigned long long)c->step, c->flag, c->st);
+            },
+            reps);
+        return ms < 0 ? ms : ms / t.ts;  // time per lattice step
+      },
+      bt);
+  if (pst != LBM_OK) return pst;
   c->tile = bt;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1408,7 +1502,6 @@ int lbm_batch_graph_captures(lbm_batch* b, int64_t* n) {
 int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth_out,
                    int32_t* steps_out) {
   if (!b) return LBM_EINVAL;
-  float best = 1e30f;
   Tile bt = b->tile;
   const int s = b->cur;
   int maxnx = 0;
@@ -1424,23 +1517,25 @@ int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth
     for (int pf : {1, 2})
       for (int L : {0, 32, 64}) cand.push_back(Tile{nw, L, pf, 2});
   }
-  for (const Tile& t : cand) {
-    int st = batch_items(b, t);
-    if (st == LBM_ENOSPACE) continue;
-    if (st != LBM_OK) return st;
-    const float ms = time_launches(
-        b->st,
-        [&] {
-          return launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items,
-                              b->nitems, b->total_rows, nullptr, (unsigned long long)b->step, b->flags, b->st);
-        },
-        5);
-    if (ms < 0) return LBM_EHIP;
-    if (ms / t.ts < best) {  // time per lattice step
-      best = ms / t.ts;
-      bt = t;
-    }
-  }
+  int ist = LBM_OK;
+  const int pst = pick_tile(
+      cand,
+      [&](const Tile& t) {
+        ist = batch_items(b, t);
+        if (ist == LBM_ENOSPACE) return 1e30f;  // too many items for the work list: skipped
+        if (ist != LBM_OK) return -1.f;
+        const float ms = time_launches(
+            b->st,
+            [&] {
+              return launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items,
+                                  b->nitems, b->total_rows, nullptr, (unsigned long long)b->step,
+                                  b->flags, b->st);
+            },
+            5);
+        return ms < 0 ? ms : ms / t.ts;  // time per lattice step
+      },
+      bt);
+  if (pst != LBM_OK) return ist != LBM_OK && ist != LBM_ENOSPACE ? ist : pst;
   batch_drop_graphs(b);
   int st = batch_items(b, bt);
   if (st != LBM_OK) return st;

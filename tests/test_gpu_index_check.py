@@ -34,15 +34,17 @@ def _faults(L):
 
 ONE = [(1, 1, 2), (1, 4, 1), (2, 0, 2), (4, 7, 2), (16, 0, 1), (8, 128, 2)]
 TWO = [(4, 0, 2, 2), (4, 1, 1, 2), (8, 5, 2, 2), (8, 0, 1, 2)]
+THREE = [(4, 0, 1, 3), (4, 1, 1, 3), (4, 64, 1, 3), (8, 0, 1, 3)]   # FP64 collision arithmetic, >= 5 x 5
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_single_lattice_tiles_in_bounds(CL, prec):
     L = CL
-    for nx, ny in [(3, 3), (5, 4), (130, 7), (260, 5), (300, 70), (257, 129)]:
+    for nx, ny in [(3, 3), (5, 4), (5, 5), (130, 7), (260, 5), (300, 70), (257, 129)]:
         gp, _ = pair(L, nx, ny, t=0.9, tau=0.9, scheme=2, sigma=0.05, precision=prec)
         rho0 = np.ascontiguousarray(0.1 + 0.02 * np.random.default_rng(nx + ny).random((ny, nx)))
-        for tile in ONE + TWO:
+        three = THREE if prec in (0, 3) and nx >= 5 and ny >= 5 else []
+        for tile in ONE + TWO + three:
             lat = L.Lattice(gp, rho0)
             lat.set_tile(*tile)
             lat.step(5)
