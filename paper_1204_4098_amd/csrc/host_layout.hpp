@@ -74,22 +74,25 @@ inline int max_items(int nx, int ny) { return ((nx + 63) / 64) * ((ny + 3) / 4);
 
 // Work list of a batch tile: per run, chunks of L rows times strips of 64*nw
 // columns, or for the two-step tile (ts = 2) strips of at most 64*nw - 6
-// columns spread evenly over the run's width (such items also suit the
-// one-step kernel, which runs an odd remainder step).  L = 0: whole-height
-// strips with row0 set for the balanced schedule.  Returns the rows of all
-// items (the balanced schedule's row space).
+// columns spread evenly over the run's width with their edges rounded down to
+// multiples of `align` columns (such items also suit the one-step kernel,
+// which runs an odd remainder step).  L = 0: whole-height strips with row0 set
+// for the balanced schedule.  Returns the rows of all items (the balanced
+// schedule's row space).
 inline int64_t build_items(int nruns, const int* nx, const int* ny, int nw, int L, int ts,
-                           std::vector<Item>& items) {
+                           std::vector<Item>& items, int align = 1) {
   items.clear();
-  const int SW = 64 * nw;
+  const int SW = 64 * nw, A = ts == 2 ? std::max(1, align) : 1;
   int64_t rows = 0;
   for (int r = 0; r < nruns; ++r) {
     const int Lr = L > 0 ? L : ny[r];
-    const int ns = ts == 2 ? (nx[r] + SW - 7) / (SW - 6) : (nx[r] + SW - 1) / SW;
+    // strips of at most SW - 6 columns once their edges are rounded down to A
+    const int ns = ts == 2 ? (nx[r] + SW - 7 - (A - 1)) / (SW - 6 - (A - 1)) : (nx[r] + SW - 1) / SW;
+    auto edge = [&](int k) { return k >= ns ? nx[r] : (int)((int64_t)k * nx[r] / ns) / A * A; };
     for (int y0 = 0; y0 < ny[r]; y0 += Lr)
       for (int sx = 0; sx < ns; ++sx) {
-        const int x0 = ts == 2 ? (int)((int64_t)sx * nx[r] / ns) : sx * SW;
-        const int x1 = ts == 2 ? (int)((int64_t)(sx + 1) * nx[r] / ns) : std::min(nx[r], x0 + SW);
+        const int x0 = ts == 2 ? edge(sx) : sx * SW;
+        const int x1 = ts == 2 ? edge(sx + 1) : std::min(nx[r], x0 + SW);
         const int n = std::min(Lr, ny[r] - y0);
         items.push_back(Item{r, x0, y0, x1 - x0, n, L > 0 ? 0 : (int32_t)std::min<int64_t>(rows, INT32_MAX)});
         rows += n;

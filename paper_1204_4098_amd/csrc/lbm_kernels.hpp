@@ -106,9 +106,8 @@ __device__ __forceinline__ void balanced_pieces(const Item* __restrict__ items, 
 struct f32s_f64a {};  // FP32 deviation storage with FP64 collision arithmetic
 template <typename S> struct Store;
 // E: stored type; R: collision arithmetic; P: type of psi, of the force and of
-// the density they are evaluated at -- FP64, except with FP16 storage, whose
-// rounding of the populations (1e-3 of the deviations) is far above the 1e-6
-// relative error of an FP32 psi (see psi2_of).  kConserve: after the FP32
+// the density they are evaluated at (FP64 for every storage type: the EOS and
+// psi stay FP64 in the reduced-precision forms).  kConserve: after the FP32
 // collision, restore the node's mass and momentum change exactly (see
 // conserve()).
 template <> struct Store<double> {
@@ -141,7 +140,7 @@ template <> struct Store<f32s_f64a> {
 template <> struct Store<__half> {
   using E = __half;
   using R = float;
-  using P = float;
+  using P = double;
   static constexpr bool kConserve = false;
   // The narrowing to FP16 takes its operand through an empty asm statement:
   // the backend otherwise folds it into the FMA that produced the operand (a
@@ -252,9 +251,7 @@ __device__ __forceinline__ R sum9(const R (&s)[9]) {
 }
 
 // psi^2 = 2 (p_EOS(rho) - rho/3) / G (Eq. 8 with Eq. 23 or Peng-Robinson), in
-// the type P.  Evaluated in FP32 from an FP32 density, psi differs from the
-// FP64 value by at most 1e-6 relative over 0.9 rho_v .. 1.02 rho_l at 0.5 to
-// 0.99 T_c (C-S a = 1, b = 4; P-R a = 2/49, b = 2/21, omega = 0.344).
+// the type P.
 template <typename P>
 __device__ __forceinline__ P psi2_of(P rho, const RunDev& d) {
 #pragma clang fp contract(off)
@@ -274,10 +271,8 @@ __device__ __forceinline__ P psi2_of(P rho, const RunDev& d) {
   return fma(rho, P(-1.0 / 3.0), p) * P(d.two_over_G);
 }
 
-// psi from psi^2: the correctly rounded FP64 square root, or the FP32
-// hardware root (1 ulp; psi^2 is a positive normal number or NaN).
+// psi from psi^2 (the correctly rounded FP64 square root).
 __device__ __forceinline__ double psi_root(double x) { return sqrt(x); }
-__device__ __forceinline__ float psi_root(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 __device__ __forceinline__ double pressure_of(double rho, const RunDev& d) {
   if (d.eos == 0) {

@@ -1261,7 +1261,9 @@ int batch_items(lbm_batch* b, const Tile& t) {
     nx[r] = b->p[r].nx;
     ny[r] = b->p[r].ny;
   }
-  const int64_t rows = layout::build_items(b->nruns, nx.data(), ny.data(), t.nw, t.L, t.ts, items);
+  // two-step strips of FP64 lattices start on 64-byte boundaries, as for a single lattice
+  const int64_t rows = layout::build_items(b->nruns, nx.data(), ny.data(), t.nw, t.L, t.ts, items,
+                                           b->prec == LBM_PREC_F64 ? Step2Align<double>::value : 1);
   if ((int)items.size() > b->items_cap) return LBM_ENOSPACE;
   if (rows >= INT32_MAX) return LBM_EINVAL;
   b->total_rows = t.L > 0 ? 0 : (int)rows;

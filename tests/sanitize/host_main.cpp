@@ -52,11 +52,12 @@ static void work_lists(std::mt19937_64& rng) {
       cap += layout::max_items(nx[r], ny[r]);
     }
     for (int nw : {1, 2, 4, 8})
-      for (int ts : {1, 2}) {
-        if (ts == 2 && nw < 4) continue;
+      for (int ts : {1, 2})
+        for (int align : {1, 8}) {
+        if ((ts == 1 && align != 1) || (ts == 2 && nw < 2)) continue;  // tiles the library offers
         for (int L : {0, 4, 5, 8, 32, 128}) {
           std::vector<Item> items;
-          const int64_t rows = layout::build_items(nruns, nx.data(), ny.data(), nw, L, ts, items);
+          const int64_t rows = layout::build_items(nruns, nx.data(), ny.data(), nw, L, ts, items, align);
           CHECK((int)items.size() <= cap);
           std::vector<std::vector<int>> cover(nruns);
           for (int r = 0; r < nruns; ++r) cover[r].assign((size_t)nx[r] * ny[r], 0);
@@ -68,6 +69,7 @@ static void work_lists(std::mt19937_64& rng) {
             CHECK(it.x0 >= 0 && it.ncols >= 1 && it.x0 + it.ncols <= nx[r]);
             CHECK(it.y0 >= 0 && it.nrows >= 1 && it.y0 + it.nrows <= ny[r]);
             CHECK(it.ncols <= (ts == 2 ? 64 * nw - 6 : 64 * nw));
+            CHECK(it.x0 % align == 0);
             if (L > 0) CHECK(it.nrows <= L && it.row0 == 0);
             else CHECK(it.row0 == prefix && it.nrows == ny[r] && it.y0 == 0);
             prefix += it.nrows;
