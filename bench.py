@@ -220,6 +220,11 @@ def main():
                      "single_step_equivalent_frac": round(
                          bpl * nx * ny / (res["kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
     }
+    rf = out["roofline"]
+    rf["copy_gbs"] = round(copy_rate(torch), 1)
+    if rf["traffic"]:
+        # HBM bytes the kernel actually moves per second, from the counter summary
+        rf["traffic_gbs"] = round(rf["traffic"] / (launch_ms * 1e-3) / 1e9, 1)
     log(f"main leg done: {out['value']} MLUPS, {out['roofline']['frac']:.3f} of HBM peak")
     legs = [] if args.legs == "none" else args.legs.split(",")
     if "precision" in legs:
@@ -349,6 +354,26 @@ def time_lattice(lbm, torch, nx, ny, rho0, kw, precision, steps, warmup, graph_s
         raise Diverged(div)
     return {"mlups": nx * ny * steps / wall / 1e6, "wall_s": wall,
             "kernel_ms": e0.elapsed_time(e1) / max(n_main, 1), "tile": tile, "graph_steps": g}
+
+
+def copy_rate(torch, mib=1024, reps=5):
+    """GB/s of a device-to-device copy of `mib` MiB (torch's copy, read plus written
+    bytes over the HIP-event time of `reps` copies): the bandwidth a plain streaming
+    kernel gets from HBM in the same process, next to the nominal 8 TB/s."""
+    a = torch.zeros(mib << 20, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del a, b
+    return 2 * (mib << 20) * reps / (ms * 1e-3) / 1e9
 
 
 def traffic_for(workload, precision, tile):

@@ -1,10 +1,11 @@
-// Host-side storage layout and batch work lists of the library, in plain C++
-// (no HIP), so that the index arithmetic can also be built with the host
-// sanitizers.  Used by lbm_lib.hip.
+// Host-side storage layout, batch work lists and the tuner's selection rule of
+// the library, in plain C++ (no HIP), so that they can also be built with the
+// host sanitizers.  Used by lbm_lib.hip.
 #pragma once
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 namespace lbm {
@@ -102,4 +103,47 @@ inline int64_t build_items(int nruns, const int* nx, const int* ny, int nw, int 
 }
 
 }  // namespace layout
+
+namespace tuning {
+
+// Index of the fastest of n candidates.  time_one(i) times candidate i
+// (milliseconds per lattice step; negative on an error; >= 1e30 to skip it).
+// A single pass in candidate order is biased by the GPU's clocks drifting down
+// over a long back-to-back run (a kernel trace of the FP64 4096 x 4096 tune
+// showed candidates late in the list running up to 40 % slower than the same
+// kernels before or after the tune).  So the first pass only shortlists the
+// kRefine fastest; they are then timed again in kRefine rounds, each round
+// starting one candidate later, so that every finalist is timed once at every
+// position of a round, and they are ranked by the sum of those times: a drift
+// that grows linearly over the calls then adds the same to every finalist's
+// sum.  Returns the index, -1 if every candidate was skipped, or -2 after an
+// error.
+constexpr int kRefine = 6;
+template <class TimeOne>
+int pick_best(int n, TimeOne&& time_one) {
+  std::vector<std::pair<float, int>> first;
+  for (int i = 0; i < n; ++i) {
+    const float ms = time_one(i);
+    if (ms < 0) return -2;
+    if (ms < 1e30f) first.push_back({ms, i});
+  }
+  if (first.empty()) return -1;
+  std::sort(first.begin(), first.end());
+  const int m = std::min<int>(kRefine, (int)first.size());
+  if (m == 1) return first[0].second;
+  std::vector<double> sum(m, 0.0);
+  for (int r = 0; r < m; ++r)
+    for (int q = 0; q < m; ++q) {
+      const int k = (q + r) % m;
+      const float ms = time_one(first[k].second);
+      if (ms < 0) return -2;
+      sum[k] += ms;
+    }
+  int kb = 0;
+  for (int k = 1; k < m; ++k)
+    if (sum[k] < sum[kb]) kb = k;
+  return first[kb].second;
+}
+
+}  // namespace tuning
 }  // namespace lbm

@@ -706,39 +706,14 @@ float time_launches(hipStream_t st, Launch&& launch, int reps) {
   return e == hipSuccess ? ms : -1.f;
 }
 
-// Pick the fastest tile per lattice step.  time_one(t) times launches of one
-// candidate (ms per lattice step; negative on a HIP error; +inf to skip it).
-// A single pass in candidate order is biased by the GPU's clocks drifting
-// down over a long back-to-back run (a kernel trace of the FP64 4096 x 4096
-// tune shows candidates late in the list running up to 40 % slower than the
-// same kernels before or after the tune), so the best kRefine of the first
-// pass are timed again in kRefineRounds rotated rounds and ranked by their
-// best time.  Returns LBM_OK or LBM_EHIP.
+// Pick the fastest tile per lattice step (tuning::pick_best); time_one(t)
+// returns ms per lattice step, negative on a HIP error, +inf to skip the tile.
+// Returns LBM_OK (best_tile unchanged if every tile was skipped) or LBM_EHIP.
 template <class TimeOne>
 int pick_tile(const std::vector<Tile>& cand, TimeOne&& time_one, Tile& best_tile) {
-  constexpr int kRefine = 6, kRefineRounds = 3;
-  std::vector<std::pair<float, int>> first;
-  for (int i = 0; i < (int)cand.size(); ++i) {
-    const float ms = time_one(cand[i]);
-    if (ms < 0) return LBM_EHIP;
-    if (ms < 1e30f) first.push_back({ms, i});
-  }
-  if (first.empty()) return LBM_OK;
-  std::sort(first.begin(), first.end());
-  const int n = std::min<int>(kRefine, (int)first.size());
-  std::vector<float> best(n);
-  for (int k = 0; k < n; ++k) best[k] = first[k].first;
-  for (int r = 0; r < kRefineRounds; ++r)
-    for (int q = 0; q < n; ++q) {
-      const int k = (q + r) % n;
-      const float ms = time_one(cand[first[k].second]);
-      if (ms < 0) return LBM_EHIP;
-      best[k] = std::min(best[k], ms);
-    }
-  int kb = 0;
-  for (int k = 1; k < n; ++k)
-    if (best[k] < best[kb]) kb = k;
-  best_tile = cand[first[kb].second];
+  const int k = tuning::pick_best((int)cand.size(), [&](int i) { return time_one(cand[i]); });
+  if (k == -2) return LBM_EHIP;
+  if (k >= 0) best_tile = cand[k];
   return LBM_OK;
 }
 

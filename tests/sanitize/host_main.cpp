@@ -4,6 +4,7 @@
 // lists of every offered tile cover each node of each run exactly once and stay
 // inside the runs, so that AddressSanitizer and UndefinedBehaviorSanitizer see
 // every index computation.  Exit status 0 when every check holds.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -84,11 +85,49 @@ static void work_lists(std::mt19937_64& rng) {
   }
 }
 
+// The tuner's selection rule under a simulated clock drift: every timing call
+// runs slower than the last, linearly up to +40 % over the whole tune (as the
+// trace of a long tune showed), so a single pass in list order favours early
+// candidates.  pick_best must return the truly fastest candidate whenever it
+// is among the six fastest measured in the first pass, skip candidates timed
+// >= 1e30 and report errors.
+static void tuner_selection(std::mt19937_64& rng) {
+  for (int trial = 0; trial < 200; ++trial) {
+    const int n = 2 + (int)(rng() % 120);
+    std::vector<float> truth(n);
+    for (float& t : truth) t = 1.0f + (float)(rng() % 1000) * 1e-3f;
+    const int fastest = (int)(std::min_element(truth.begin(), truth.end()) - truth.begin());
+    const int m = std::min(n, lbm::tuning::kRefine);
+    const int total_calls = n + m * m;
+    int calls = 0;
+    auto drifting = [&](int i) {
+      const float slow = 1.0f + 0.4f * (float)calls / (float)total_calls;
+      ++calls;
+      return truth[i] * slow;
+    };
+    // a single pass would see candidate i at truth[i] * (1 + 0.4 i / total)
+    int first_pass_rank = 0;
+    for (int i = 0; i < n; ++i)
+      if (truth[i] * (1.0f + 0.4f * (float)i / (float)total_calls) <
+          truth[fastest] * (1.0f + 0.4f * (float)fastest / (float)total_calls))
+        ++first_pass_rank;
+    const int k = lbm::tuning::pick_best(n, drifting);
+    CHECK(k >= 0 && k < n);
+    if (first_pass_rank < lbm::tuning::kRefine) CHECK(k == fastest);
+    CHECK(calls == n + (m > 1 ? m * m : 0));
+  }
+  // skipped candidates and errors
+  CHECK(lbm::tuning::pick_best(3, [](int) { return 1e30f; }) == -1);
+  CHECK(lbm::tuning::pick_best(3, [](int i) { return i == 1 ? 1e30f : 2.0f - i; }) == 2);
+  CHECK(lbm::tuning::pick_best(4, [](int i) { return i == 2 ? -1.0f : 1.0f; }) == -2);
+}
+
 int main() {
   std::mt19937_64 rng(0x12044098);
   const int shapes[][2] = {{3, 3}, {5, 4}, {64, 16}, {70, 9}, {130, 7}, {257, 3}};
   for (const auto& s : shapes) round_trips(s[0], s[1], rng);
   work_lists(rng);
+  tuner_selection(rng);
   std::printf("host layout sanitizer driver: %d failed checks\n", failures);
   return failures != 0;
 }
