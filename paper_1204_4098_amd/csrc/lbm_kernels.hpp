@@ -685,6 +685,11 @@ constexpr int kRowPsi = 1, kRowPull2 = 2, kRowCollide1 = 4, kRowCollide2 = 8, kR
 template <typename S> struct SteadyMode
     : std::integral_constant<int, kRowSteady | kRowPsi | kRowPull2 | kRowCollide1 | kRowCollide2> {};
 template <> struct SteadyMode<double> : std::integral_constant<int, kRowSteady | kRowPull2> {};
+// The batched kernel unmasks every phase for every storage type: on the
+// 256-run sweep (2-wave strips of 16-64-row lattices) that is 2 % faster for
+// FP64 storage (44.3 -> 45.3 GLUPS), while on the 4096 x 4096 lattice it makes
+// the single-lattice FP64 kernel 5 % slower (485 -> 513 us per launch).
+constexpr int kBatchSteadyMode = kRowSteady | kRowPsi | kRowPull2 | kRowCollide1 | kRowCollide2;
 // Steady rows per loop iteration (1 to 3), measured likewise.  Unrolling by 3
 // removes the rotation moves but adds registers; it pays only for FP32
 // storage with FP64 arithmetic (FP64 storage: 7 % fewer VALU instructions per
@@ -708,7 +713,7 @@ template <> struct SteadyUnroll<f32s_f64a> : std::integral_constant<int, 3> {};
 // behind step one; one row of the march takes two barriers.  Both steps use
 // the same arithmetic, in the same order, as two single-step launches, so the
 // result is bitwise identical.
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, int MODE = SteadyMode<S>::value>
 __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restrict__ src,
                                            typename Store<S>::E* __restrict__ dst,
                                            const RunDev& d, int x0, int y0, int ncols, int nrows,
@@ -757,7 +762,8 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   R hp[9] = {};     // step-two pulled populations of the row collided next
   P psi2p = P(0);
   const int n_one = nrows + 4;                      // step-one rows y0-2 .. y0+nrows+1
-  // One row of the march.  Mode (SteadyMode) bit 16 marks a steady row, in
+  // One row of the march.  Mode (MODE: SteadyMode, or kBatchSteadyMode in the
+  // batched kernel) bit 16 marks a steady row, in
   // which every row condition below holds; bits 1, 2, 4, 8 make a phase run
   // on every lane of the block: lanes outside the phase's range compute values
   // that no lane in range reads (their LDS slots are read only by lanes
@@ -862,7 +868,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
   };
   // rows 0..4 fill the pipeline, 5 .. n_one-2 are steady, the last two drain it
   using Edge = std::integral_constant<int, 0>;
-  using Steady = std::integral_constant<int, SteadyMode<S>::value>;
+  using Steady = std::integral_constant<int, MODE>;
   for (int j = 0; j < 5; ++j) row(j, Edge{});
   // Steady rows U at a time (a loop with barriers is not unrolled by the
   // compiler): with U = 3, the period of the kept-row rotations (gA -> gB ->
@@ -1290,8 +1296,9 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>
                       if (flags[it.run] < step)
                         copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0 + y, it.ncols, n);
                       else
-                        tile_step2<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0 + y, it.ncols, n,
-                                              step, &flags[it.run], ring1, ring2, xch);
+                        tile_step2<S, NW, PF, kBatchSteadyMode>(src + d.off, dst + d.off, d, it.x0,
+                                                                it.y0 + y, it.ncols, n, step,
+                                                                &flags[it.run], ring1, ring2, xch);
                     });
     return;
   }
@@ -1303,8 +1310,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>
     if (flags[it.run] < step)  // frozen run
       copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows);
     else
-      tile_step2<S, NW, PF>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows, step,
-                            &flags[it.run], ring1, ring2, xch);
+      tile_step2<S, NW, PF, kBatchSteadyMode>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols,
+                                              it.nrows, step, &flags[it.run], ring1, ring2, xch);
     __syncthreads();  // LDS is reused by the next item
   }
 }
