@@ -231,8 +231,11 @@ class Lattice:
         return g.value
 
     def moments_device(self):
+        """(rho, vx, vy, p) as device tensors; the library writes them on the
+        lattice's stream, and the caller's current stream is made to wait for it."""
         out = [torch.empty((self.p.ny, self.p.nx), dtype=torch.float64, device=self.device) for _ in range(4)]
         _check(lib().lbm_moments_device(self.ctx, *[o.data_ptr() for o in out]), "lbm_moments_device")
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return tuple(out)
 
     def mass(self):

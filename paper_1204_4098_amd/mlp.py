@@ -129,12 +129,14 @@ class Mlp:
         hist = []
         torch.cuda.current_stream(self.device).synchronize()
         nb = max(1, n // batch)
-        perm = torch.randperm(n, generator=g).to(self.device)
+        perm = None
         for s in range(steps):
             k = s % nb
-            if k == 0 and s > 0:
-                perm = torch.randperm(n, generator=g).to(self.device)
             with torch.cuda.stream(self.stream):
+                if k == 0:
+                    # each epoch's permutation is copied on the training stream, so
+                    # the minibatch gathers below are ordered after the copy
+                    perm = torch.randperm(n, generator=g).to(self.device)
                 idx = perm[k * batch:(k + 1) * batch]
                 xb = Xd.index_select(0, idx).contiguous()
                 tb = Td.index_select(0, idx).contiguous()
