@@ -691,11 +691,14 @@ template <> struct SteadyMode<double> : std::integral_constant<int, kRowSteady |
 // the single-lattice FP64 kernel 5 % slower (485 -> 513 us per launch).
 constexpr int kBatchSteadyMode = kRowSteady | kRowPsi | kRowPull2 | kRowCollide1 | kRowCollide2;
 // Steady rows per loop iteration (1 to 3), measured likewise.  Unrolling by 3
-// removes the rotation moves but adds registers; it pays only for FP32
-// storage with FP64 arithmetic (FP64 storage: 7 % fewer VALU instructions per
-// row yet 5 % slower; FP32 and FP16: 3 waves per SIMD would drop to 2).
+// removes the rotation moves but adds registers; it pays for FP32 storage with
+// FP64 arithmetic and for FP16 storage (261 -> 251 us per launch, 161-167
+// VGPRs: still 3 waves per SIMD); FP64 storage: 7 % fewer VALU instructions
+// per row yet 5 % slower; FP32 storage would fall from 3 to 2 waves per SIMD
+// (241 VGPRs).
 template <typename S> struct SteadyUnroll : std::integral_constant<int, 1> {};
 template <> struct SteadyUnroll<f32s_f64a> : std::integral_constant<int, 3> {};
+template <> struct SteadyUnroll<__half> : std::integral_constant<int, 3> {};
 
 // The populations cross HBM once per two steps.  Lane i of a block owns
 // column c = x0 - 3 + i for both steps, i < ncols + 6:
