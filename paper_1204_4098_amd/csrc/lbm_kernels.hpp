@@ -716,7 +716,7 @@ template <> struct SteadyUnroll<__half> : std::integral_constant<int, 3> {};
 // behind step one; one row of the march takes two barriers.  Both steps use
 // the same arithmetic, in the same order, as two single-step launches, so the
 // result is bitwise identical.
-template <typename S, int NW, int PF, int MODE = SteadyMode<S>::value>
+template <typename S, int NW, int PF, int MODE = SteadyMode<S>::value, bool MRT = false>
 __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restrict__ src,
                                            typename Store<S>::E* __restrict__ dst,
                                            const RunDev& d, int x0, int y0, int ncols, int nrows,
@@ -832,7 +832,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
         const bool chk = out && y1 >= y0 && y1 < y0 + nrows;
         bad1 |= chk && (!(psi2c > P(0)) || !(rho > P(0)));
         const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
-        update_node<S, false>(fc, drho, rho, Fx, Fy, ip2, d);
+        update_node<S, MRT>(fc, drho, rho, Fx, Fy, ip2, d);
 #pragma unroll
         for (int a = 0; a < 9; ++a) gA[a] = T::round(fc[a]);
       }
@@ -855,7 +855,7 @@ __device__ __forceinline__ void tile_step2(const typename Store<S>::E* __restric
       const P rho = rref + P(drho);
       bad2 |= out && (!(psi2p > P(0)) || !(rho > P(0)));
       const R ip2 = d.sig != 0.0 ? rcp(R(psi2p)) : R(0);
-      update_node<S, false>(hp, drho, rho, Fx, Fy, ip2, d);
+      update_node<S, MRT>(hp, drho, rho, Fx, Fy, ip2, d);
       if (out) {
         typename T::E* orow = dst + (int64_t)wrapy(r) * d.rs;
 #pragma unroll
@@ -910,7 +910,7 @@ template <> struct Step2Align<double> : std::integral_constant<int, 8> {};
 // share is split where it crosses a strip boundary.  (With the row-interleaved
 // layout a band-major order -- the blocks of one XCD marching one band of rows
 // across all strips -- measured no faster for any storage type.)
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT = false>
 __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* __restrict__ src,
                                                    typename Store<S>::E* __restrict__ dst,
                                                    RunDev d, int L, int nstrips,
@@ -940,7 +940,8 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
     if (frozen)
       copy_tile<S, 64 * NW>(src, dst, d, x0, y0, nc, min(L, d.ny - y0));
     else
-      tile_step2<S, NW, PF>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2,
+      tile_step2<S, NW, PF, SteadyMode<S>::value, MRT>(src, dst, d, x0, y0, nc, min(L, d.ny - y0),
+                                                       step, flag, ring1, ring2,
                             xch);
     return;
   }
@@ -955,7 +956,8 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
     if (frozen)
       copy_tile<S, 64 * NW>(src, dst, d, x0, y, nc, n);
     else
-      tile_step2<S, NW, PF>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, xch);
+      tile_step2<S, NW, PF, SteadyMode<S>::value, MRT>(src, dst, d, x0, y, nc, n, step, flag, ring1,
+                                                       ring2, xch);
     r += n;
     __syncthreads();  // LDS is reused by the next piece
   }

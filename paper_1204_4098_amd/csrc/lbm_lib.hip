@@ -255,7 +255,7 @@ hipError_t launch_step_s(const Tile& t, const void* src, void* dst, const RunDev
   }
 }
 
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT = false>
 hipError_t launch_step2_t(const void* src, void* dst, const RunDev& d, int L,
                           const unsigned long long* base, unsigned long long local,
                           unsigned long long* flag, hipStream_t st) {
@@ -268,24 +268,24 @@ hipError_t launch_step2_t(const void* src, void* dst, const RunDev& d, int L,
     grid = nstrips * ((d.ny + L - 1) / L);
   } else {
     const int64_t rows = (int64_t)nstrips * d.ny;
-    grid = resident_blocks((const void*)k_step2<S, NW, PF>, SW);
+    grid = resident_blocks((const void*)k_step2<S, NW, PF, MRT>, SW);
     grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, rows / 8));
   }
   using E = typename Store<S>::E;
-  hipLaunchKernelGGL((k_step2<S, NW, PF>), dim3(grid), dim3(SW), 0, st, static_cast<const E*>(src),
-                     static_cast<E*>(dst), d, L, nstrips, base, local, flag);
+  hipLaunchKernelGGL((k_step2<S, NW, PF, MRT>), dim3(grid), dim3(SW), 0, st,
+                     static_cast<const E*>(src), static_cast<E*>(dst), d, L, nstrips, base, local, flag);
   return hipGetLastError();
 }
 
-template <typename S>
+template <typename S, bool MRT = false>
 hipError_t launch_step2_s(const Tile& t, const void* src, void* dst, const RunDev& d,
                           const unsigned long long* base, unsigned long long local,
                           unsigned long long* flag, hipStream_t st) {
   switch (t.nw * 10 + t.pf) {
-    case 41: return launch_step2_t<S, 4, 1>(src, dst, d, t.L, base, local, flag, st);
-    case 42: return launch_step2_t<S, 4, 2>(src, dst, d, t.L, base, local, flag, st);
-    case 81: return launch_step2_t<S, 8, 1>(src, dst, d, t.L, base, local, flag, st);
-    default: return launch_step2_t<S, 8, 2>(src, dst, d, t.L, base, local, flag, st);
+    case 41: return launch_step2_t<S, 4, 1, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 42: return launch_step2_t<S, 4, 2, MRT>(src, dst, d, t.L, base, local, flag, st);
+    case 81: return launch_step2_t<S, 8, 1, MRT>(src, dst, d, t.L, base, local, flag, st);
+    default: return launch_step2_t<S, 8, 2, MRT>(src, dst, d, t.L, base, local, flag, st);
   }
 }
 
@@ -328,6 +328,10 @@ hipError_t launch_step(int prec, const Tile& t, const void* src, void* dst, cons
       return t.nw == 8 ? launch_step3_t<f32s_f64a, 8>(src, dst, d, t.L, base, local, flag, st)
                        : launch_step3_t<f32s_f64a, 4>(src, dst, d, t.L, base, local, flag, st);
     return hipErrorInvalidValue;
+  }
+  if (t.ts == 2 && d.mrt) {  // FP64 or FP32 deviation storage (checked by lbm_set_mrt)
+    if (prec == LBM_PREC_F64) return launch_step2_s<double, true>(t, src, dst, d, base, local, flag, st);
+    return launch_step2_s<float, true>(t, src, dst, d, base, local, flag, st);
   }
   if (t.ts == 2) {
     if (prec == LBM_PREC_F64) return launch_step2_s<double>(t, src, dst, d, base, local, flag, st);
@@ -1021,7 +1025,7 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
 
 int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
   if (!c || !valid_tile(nw, L, depth, 16, steps)) return LBM_EINVAL;
-  if (c->d.mrt && steps != 1) return LBM_ENOTSUP;
+  if (c->d.mrt && steps == 3) return LBM_ENOTSUP;
   if (steps == 3 && !has_step3(c->p.precision)) return LBM_ENOTSUP;
   if (steps == 3 && (c->p.nx < 5 || c->p.ny < 5)) return LBM_EINVAL;  // halo of 5 wraps once
   c->tile = Tile{nw, L, depth, steps};
@@ -1052,7 +1056,7 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, in
           cand.push_back(Tile{nw, L, pf, 1});
   }
   for (int nw : kStep2Waves) {
-    if (c->d.mrt || (nw > 4 && 64 * (nw / 2) >= c->p.nx)) continue;
+    if (nw > 4 && 64 * (nw / 2) >= c->p.nx) continue;
     for (int pf : {1, 2})
       for (int L : {0, 32, 64, 128})
         if (L <= 2 * c->p.ny) cand.push_back(Tile{nw, L, pf, 2});
@@ -1113,7 +1117,7 @@ int lbm_set_mrt(lbm_ctx* c, const double* rates) {
     if (!(rates[i] > 0.0 && rates[i] < 2.0)) return LBM_EINVAL;
   c->d = make_rundev(c->p, c->k, c->p.rho_ref, 0, 0);
   set_mrt(c->d, c->p, rates);
-  if (c->tile.ts != 1) c->tile = Tile{c->tile.nw, c->tile.L, c->tile.pf, 1};
+  if (c->tile.ts == 3) c->tile = Tile{c->tile.nw, c->tile.L, c->tile.pf, 1};
   drop_graphs(c);  // the captured launches carry the old constants
   return prepare_graphs(c);
 }

@@ -54,10 +54,30 @@ def test_mrt_slab_matches_oracle(L, rates):
     assert max(errs) < TOL64, errs
 
 
-def test_mrt_peng_robinson_droplet_ragged_tile(L):
+@pytest.mark.parametrize("tile", [(2, 16, 1), (4, 16, 1, 2)])
+def test_mrt_peng_robinson_droplet_ragged_tile(L, tile):
     gp, op = _mrt_pair(L, 130, 70, t=0.85, tau=0.9, scheme=2, sigma=0.105, eos=PR)
-    errs = _run(L, gp, op, droplet_rho(130, 70, PR, 0.85, 20), [1, 50, 500], tile=(2, 16, 1))
+    errs = _run(L, gp, op, droplet_rho(130, 70, PR, 0.85, 20), [1, 50, 500], tile=tile)
     assert max(errs) < TOL64, errs
+
+
+def test_mrt_f32_two_step_bitwise(L):
+    """FP32 deviation storage: the two-step kernel rounds its intermediate step to
+    storage as the one-step kernel does, so the two agree bit for bit."""
+    gp, _ = pair(L, 200, 90, t=0.8, tau=0.7, scheme=2, sigma=0.1, precision=1)
+    rho0 = slab_rho(200, 90, CS, 0.8, seed=5)
+    outs = []
+    for tile, graph in [((4, 0, 2), 0), ((4, 0, 2, 2), 0), ((8, 16, 1, 2), 10)]:
+        lat = L.Lattice(gp, rho0)
+        lat.set_mrt(RATES)
+        lat.set_tile(*tile)
+        if graph:
+            lat.set_graph_steps(graph)
+        lat.step(3)
+        lat.step(34)
+        outs.append(lat.save_state())
+        lat.close()
+    assert all(o == outs[0] for o in outs[1:])
 
 
 def test_mrt_every_rate_one_over_tau_is_bgk(L):
@@ -77,7 +97,8 @@ def test_mrt_tiles_and_graphs_bitwise(L):
     gp, _ = pair(L, 200, 90, t=0.8, tau=0.7, scheme=2, sigma=0.1)
     rho0 = slab_rho(200, 90, CS, 0.8, seed=3)
     outs = []
-    for tile, graph in [((1, 4, 1), 0), ((4, 0, 2), 0), ((16, 7, 1), 0), ((2, 0, 2), 10)]:
+    for tile, graph in [((1, 4, 1), 0), ((4, 0, 2), 0), ((16, 7, 1), 0), ((2, 0, 2), 10),
+                        ((4, 0, 2, 2), 0), ((8, 5, 1, 2), 0), ((4, 32, 1, 2), 10), ((8, 0, 2, 2), 12)]:
         lat = L.Lattice(gp, rho0)
         lat.set_mrt(RATES)
         lat.set_tile(*tile)
@@ -120,10 +141,14 @@ def test_mrt_arguments(L):
         assert e.value.status == L.LBM_EINVAL
     lat.set_tile(4, 0, 2, 2)
     lat.set_mrt(RATES)
-    assert lat.get_tile() == (4, 0, 2, 1)          # two-step tile becomes one step per launch
+    assert lat.get_tile() == (4, 0, 2, 2)          # the two-step kernel carries MRT
+    lat.set_mrt(None)
+    lat.set_tile(4, 0, 1, 3)
+    lat.set_mrt(RATES)                             # a three-step tile becomes one step
+    assert lat.get_tile() == (4, 0, 1, 1)
     with pytest.raises(L.LbmError) as e:
-        lat.set_tile(4, 0, 2, 2)
+        lat.set_tile(4, 0, 1, 3)
     assert e.value.status == L.LBM_ENOTSUP
-    lat.set_mrt(None)                              # back to BGK: two steps allowed again
-    lat.set_tile(4, 0, 2, 2)
+    lat.set_mrt(None)                              # back to BGK: three steps allowed again
+    lat.set_tile(4, 0, 1, 3)
     lat.close()

@@ -154,7 +154,7 @@ def test_three_step_rejected_where_unsupported(L):
     for tile in [(16, 0, 1, 3), (4, 0, 2, 3), (2, 0, 1, 3)]:
         with pytest.raises(L.LbmError):
             lat.set_tile(*tile)
-    # the MRT collision runs one step per launch: a three-step tile is refused, and
+    # the three-step kernel has no MRT collision: a three-step tile is refused, and
     # switching to MRT turns a three-step tile into the one-step tile of the same shape
     lat.set_tile(4, 0, 1, 3)
     lat.set_mrt((1.3, 1.1, 1.2))
