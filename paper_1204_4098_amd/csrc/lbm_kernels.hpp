@@ -528,6 +528,16 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
   const P rref = P(d.rho_ref);
   bool bad = false;
 
+  // preload rows y0-1 (ring slot 0) and y0 (slot 1); with PF = 2 also issue row
+  // y0+1.  The loads are issued before the halo prologue so that both wait on
+  // memory together.
+  R fc[9], fn[9], fp[9];
+  if (act) {
+    pull9<S>(src, d, cx, y0 == 0 ? d.ny - 1 : y0 - 1, fp);
+    pull9<S>(src, d, cx, y0, fc);
+    if (PF == 2) pull9<S>(src, d, cx, y0 + 1 == d.ny ? 0 : y0 + 1, fn);
+  }
+
   // prologue: psi of the two halo columns for rows y0-1 .. y0+nrows
   for (int i = tid; i < 2 * (nrows + 2); i += SW) {
     const int k = i >> 1;
@@ -539,15 +549,9 @@ __device__ __forceinline__ void tile_step(const typename Store<S>::E* __restrict
     ((i & 1) ? haloR : haloL)[k] = psi_root(psi2_of(rho, d));
   }
 
-  // preload rows y0-1 (ring slot 0) and y0 (slot 1); with PF = 2 also issue row y0+1
-  R fc[9], fn[9];
   P psi2c = P(0);
   if (act) {
-    R f[9];
-    pull9<S>(src, d, cx, y0 == 0 ? d.ny - 1 : y0 - 1, f);
-    pull9<S>(src, d, cx, y0, fc);
-    if (PF == 2) pull9<S>(src, d, cx, y0 + 1 == d.ny ? 0 : y0 + 1, fn);
-    ring[0][tid + 1] = psi_root(psi2_of(rref + P(sum9(f)), d));
+    ring[0][tid + 1] = psi_root(psi2_of(rref + P(sum9(fp)), d));
     psi2c = psi2_of(rref + P(sum9(fc)), d);
     ring[1][tid + 1] = psi_root(psi2c);
   }
