@@ -238,17 +238,19 @@ def main():
                                                  "frac": round(gbs / PEAK_HBM_GBS, 4),
                                                  "bytes_per_lup": BYTES_PER_LUP[prec] / r["tile"][3]}
             log(f"precision {PREC_NAME[prec]}: {r['mlups']:.0f} MLUPS")
-        # the FP64 two-step kernel on the same workload, for its own roofline
-        # fraction when the tuner has picked the three-step one
-        r = time_lattice(lbm, torch, nx, ny, rho0, kw, 0, args.steps, args.warmup, args.graph_steps,
-                         False, (4, 0, 2, 2), settle_ms=args.settle_ms)
-        gbs = BYTES_PER_LUP[0] * nx * ny / (r["kernel_ms"] * 2 * 1e-3) / 1e9
-        out["precision"]["f64_two_step"] = {"mlups": round(r["mlups"], 1), "tile": r["tile"],
-                                            "kernel_avg_us": round(r["kernel_ms"] * 2e3, 2),
-                                            "achieved_gbs": round(gbs, 1),
-                                            "frac": round(gbs / PEAK_HBM_GBS, 4),
-                                            "traffic": traffic_for(args.workload, 0, r["tile"])}
-        log(f"f64 two-step: {r['mlups']:.0f} MLUPS")
+        # the FP64 one- and two-step kernels on the same workload, each with its own
+        # roofline fraction (per launch: every population read and written once),
+        # when the tuner has picked the three-step one
+        for name, t1 in (("f64_one_step", (16, 0, 1, 1)), ("f64_two_step", (4, 0, 2, 2))):
+            r = time_lattice(lbm, torch, nx, ny, rho0, kw, 0, args.steps, args.warmup,
+                             args.graph_steps, False, t1, settle_ms=args.settle_ms)
+            gbs = BYTES_PER_LUP[0] * nx * ny / (r["kernel_ms"] * t1[3] * 1e-3) / 1e9
+            out["precision"][name] = {"mlups": round(r["mlups"], 1), "tile": r["tile"],
+                                      "kernel_avg_us": round(r["kernel_ms"] * t1[3] * 1e3, 2),
+                                      "achieved_gbs": round(gbs, 1),
+                                      "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                      "traffic": traffic_for(args.workload, 0, r["tile"])}
+            log(f"{name}: {r['mlups']:.0f} MLUPS, {gbs / PEAK_HBM_GBS:.3f} of HBM peak")
     if "droplet1024" in legs and args.workload != "droplet1024":
         d = {}
         for t in (0.6, 0.8):
