@@ -224,8 +224,8 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes);
  * lbm_step(n) smaller than `steps` runs as one launch of that many steps.
  * waves in {1, 2, 4, 8, 16}; rows in [0, 128].  lbm_tune times the candidates
  * on the current state without advancing it and keeps the fastest per lattice
- * step; the choice is cached per (nx, ny, precision) for the life of the
- * process.  Every tile gives bitwise identical results. */
+ * step; the choice is cached per (nx, ny, precision, collision operator) for
+ * the life of the process.  Every tile gives bitwise identical results. */
 int lbm_tune(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
 int lbm_set_tile(lbm_ctx* c, int32_t waves, int32_t rows, int32_t depth, int32_t steps);
 int lbm_get_tile(lbm_ctx* c, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
