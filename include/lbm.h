@@ -312,6 +312,14 @@ int lbm_batch_set_tile(lbm_batch* b, int32_t waves, int32_t rows, int32_t depth,
 int lbm_batch_get_tile(lbm_batch* b, int32_t* waves, int32_t* rows, int32_t* depth, int32_t* steps);
 /* As lbm_set_graph_steps: captures the graphs of both parities now. */
 int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k);
+/* The MRT collision of lbm_set_mrt for every run of the batch: rates[3*i ..
+ * 3*i+2] = s_e, s_eps, s_q of run i (each in (0, 2), else LBM_EINVAL);
+ * rates = NULL restores BGK.  Every run must use the improved scheme and the
+ * batch FP64 or FP32 deviation storage (else LBM_ENOTSUP; nothing changes on
+ * an error).  One- and two-step batch tiles; each run's results are bitwise
+ * those of a single lattice with the same rates.  The descriptor table is
+ * uploaded and captured graphs are rebuilt (synchronous). */
+int lbm_batch_set_mrt(lbm_batch* b, const double* rates);
 int lbm_batch_graph_captures(lbm_batch* b, int64_t* n);
 /* Lattice updates per step summed over runs that are still active. */
 int lbm_batch_nodes(lbm_batch* b, int64_t* nodes);

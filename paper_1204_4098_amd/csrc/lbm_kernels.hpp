@@ -1284,7 +1284,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step(const typename Store<S>:
 // Persistent batched launch of two steps (tile_step2) over a work list whose
 // items are at most 64*NW - 6 columns wide.  A run frozen by divergence at an
 // earlier launch is copied unchanged; grid must be a multiple of 8.
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT = false>
 __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>::E* __restrict__ src,
                                                          typename Store<S>::E* __restrict__ dst,
                                                          const RunDev* __restrict__ runs,
@@ -1305,9 +1305,10 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>
                       if (flags[it.run] < step)
                         copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0 + y, it.ncols, n);
                       else
-                        tile_step2<S, NW, PF, kBatchSteadyMode>(src + d.off, dst + d.off, d, it.x0,
-                                                                it.y0 + y, it.ncols, n, step,
-                                                                &flags[it.run], ring1, ring2, xch);
+                        tile_step2<S, NW, PF, kBatchSteadyMode, MRT>(src + d.off, dst + d.off, d,
+                                                                     it.x0, it.y0 + y, it.ncols, n,
+                                                                     step, &flags[it.run], ring1,
+                                                                     ring2, xch);
                     });
     return;
   }
@@ -1319,8 +1320,9 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const typename Store<S>
     if (flags[it.run] < step)  // frozen run
       copy_tile<S, 64 * NW>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols, it.nrows);
     else
-      tile_step2<S, NW, PF, kBatchSteadyMode>(src + d.off, dst + d.off, d, it.x0, it.y0, it.ncols,
-                                              it.nrows, step, &flags[it.run], ring1, ring2, xch);
+      tile_step2<S, NW, PF, kBatchSteadyMode, MRT>(src + d.off, dst + d.off, d, it.x0, it.y0,
+                                                   it.ncols, it.nrows, step, &flags[it.run], ring1,
+                                                   ring2, xch);
     __syncthreads();  // LDS is reused by the next item
   }
 }

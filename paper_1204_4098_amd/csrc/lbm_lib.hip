@@ -360,64 +360,77 @@ int batch_grid(const void* fn, int threads, int nitems, int total) {
   return std::max(8, g / 8 * 8);
 }
 
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT>
 hipError_t launch_batch_t(const void* src, void* dst, const RunDev* runs, const Item* items,
                           int nitems, int total, const unsigned long long* base,
                           unsigned long long local, unsigned long long* flags, hipStream_t st) {
-  const int g = batch_grid((const void*)k_batch_step<S, NW, PF>, 64 * NW, nitems, total);
+  const int g = batch_grid((const void*)k_batch_step<S, NW, PF, MRT>, 64 * NW, nitems, total);
   using E = typename Store<S>::E;
-  hipLaunchKernelGGL((k_batch_step<S, NW, PF>), dim3(g), dim3(64 * NW), 0, st,
+  hipLaunchKernelGGL((k_batch_step<S, NW, PF, MRT>), dim3(g), dim3(64 * NW), 0, st,
                      static_cast<const E*>(src), static_cast<E*>(dst), runs, items, nitems, total,
                      base, local, flags);
   return hipGetLastError();
 }
 
-template <typename S>
+template <typename S, bool MRT = false>
 hipError_t launch_batch_s(const Tile& t, const void* src, void* dst, const RunDev* runs,
                           const Item* items, int nitems, int total, const unsigned long long* base,
                           unsigned long long local, unsigned long long* flags, hipStream_t st) {
   switch (t.nw * 10 + t.pf) {
-    case 11: return launch_batch_t<S, 1, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 12: return launch_batch_t<S, 1, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 21: return launch_batch_t<S, 2, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 22: return launch_batch_t<S, 2, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 41: return launch_batch_t<S, 4, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 42: return launch_batch_t<S, 4, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 81: return launch_batch_t<S, 8, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    default: return launch_batch_t<S, 8, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 11: return launch_batch_t<S, 1, 1, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 12: return launch_batch_t<S, 1, 2, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 21: return launch_batch_t<S, 2, 1, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 22: return launch_batch_t<S, 2, 2, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 41: return launch_batch_t<S, 4, 1, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 42: return launch_batch_t<S, 4, 2, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 81: return launch_batch_t<S, 8, 1, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    default: return launch_batch_t<S, 8, 2, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
   }
 }
 
-template <typename S, int NW, int PF>
+template <typename S, int NW, int PF, bool MRT>
 hipError_t launch_batch2_t(const void* src, void* dst, const RunDev* runs, const Item* items,
                            int nitems, int total, const unsigned long long* base,
                            unsigned long long local, unsigned long long* flags, hipStream_t st) {
-  const int g = batch_grid((const void*)k_batch_step2<S, NW, PF>, 64 * NW, nitems, total);
+  const int g = batch_grid((const void*)k_batch_step2<S, NW, PF, MRT>, 64 * NW, nitems, total);
   using E = typename Store<S>::E;
-  hipLaunchKernelGGL((k_batch_step2<S, NW, PF>), dim3(g), dim3(64 * NW), 0, st,
+  hipLaunchKernelGGL((k_batch_step2<S, NW, PF, MRT>), dim3(g), dim3(64 * NW), 0, st,
                      static_cast<const E*>(src), static_cast<E*>(dst), runs, items, nitems, total,
                      base, local, flags);
   return hipGetLastError();
 }
 
-template <typename S>
+template <typename S, bool MRT = false>
 hipError_t launch_batch2_s(const Tile& t, const void* src, void* dst, const RunDev* runs,
                            const Item* items, int nitems, int total, const unsigned long long* base,
                            unsigned long long local, unsigned long long* flags, hipStream_t st) {
   switch (t.nw * 10 + t.pf) {
-    case 21: return launch_batch2_t<S, 2, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 22: return launch_batch2_t<S, 2, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 41: return launch_batch2_t<S, 4, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 42: return launch_batch2_t<S, 4, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    case 81: return launch_batch2_t<S, 8, 1>(src, dst, runs, items, nitems, total, base, local, flags, st);
-    default: return launch_batch2_t<S, 8, 2>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 21: return launch_batch2_t<S, 2, 1, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 22: return launch_batch2_t<S, 2, 2, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 41: return launch_batch2_t<S, 4, 1, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 42: return launch_batch2_t<S, 4, 2, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    case 81: return launch_batch2_t<S, 8, 1, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
+    default: return launch_batch2_t<S, 8, 2, MRT>(src, dst, runs, items, nitems, total, base, local, flags, st);
   }
 }
 
-// One launch of the batch tile: t.ts time steps (1 or 2) of every active run.
-hipError_t launch_batch(int prec, const Tile& t, const void* src, void* dst, const RunDev* runs,
-                        const Item* items, int nitems, int total, const unsigned long long* base,
-                        unsigned long long local, unsigned long long* flags, hipStream_t st) {
+// One launch of the batch tile: t.ts time steps (1 or 2) of every active run;
+// mrt: the runs' descriptors carry the MRT collision (FP64 or FP32 deviation
+// storage, checked by lbm_batch_set_mrt).
+hipError_t launch_batch(int prec, bool mrt, const Tile& t, const void* src, void* dst,
+                        const RunDev* runs, const Item* items, int nitems, int total,
+                        const unsigned long long* base, unsigned long long local,
+                        unsigned long long* flags, hipStream_t st) {
+  if (mrt) {
+    if (t.ts == 2) {
+      if (prec == LBM_PREC_F64)
+        return launch_batch2_s<double, true>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
+      return launch_batch2_s<float, true>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
+    }
+    if (prec == LBM_PREC_F64)
+      return launch_batch_s<double, true>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
+    return launch_batch_s<float, true>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
+  }
   if (t.ts == 2) {
     if (prec == LBM_PREC_F64)
       return launch_batch2_s<double>(t, src, dst, runs, items, nitems, total, base, local, flags, st);
@@ -1198,6 +1211,7 @@ struct lbm_batch {
   Tile gtile;
   int64_t captures;  // graphs captured so far
   double* coex;      // 2 * nruns doubles: (rho_l, rho_g) per run
+  int mrt;           // 1: every run's descriptor carries the MRT collision
 };
 
 namespace {
@@ -1268,7 +1282,7 @@ int batch_capture(lbm_batch* b, int parity) {
   const int launches = b->graph_k / b->tile.ts;  // graph_k is even
   for (int i = 0; i < launches && e == hipSuccess; ++i) {
     const int s = (parity + i) & 1;
-    e = launch_batch(b->prec, b->tile, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems, b->total_rows,
+    e = launch_batch(b->prec, b->mrt != 0, b->tile, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems, b->total_rows,
                      b->ctr, (unsigned long long)i * b->tile.ts, b->flags, b->st);
   }
   if (e == hipSuccess) {
@@ -1309,7 +1323,7 @@ std::tuple<int, int, int, int> batch_key(const lbm_batch* b) {
     tot += b->nodes[r];
     maxnx = std::max(maxnx, b->p[r].nx);
   }
-  return {(int)std::min<int64_t>(tot, INT32_MAX), maxnx, b->prec, b->nruns};
+  return {(int)std::min<int64_t>(tot, INT32_MAX), maxnx, b->prec | (b->mrt << 8), b->nruns};
 }
 
 }  // namespace
@@ -1441,7 +1455,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
     const int s = b->cur;
     Tile t = b->tile;
     if (n - done < t.ts) t.ts = 1;  // odd remainder of a two-step tile (its items suit both)
-    HIPCHK(launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems, b->total_rows,
+    HIPCHK(launch_batch(b->prec, b->mrt != 0, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items, b->nitems, b->total_rows,
                         nullptr, (unsigned long long)b->step, b->flags, b->st));
     b->cur ^= 1;
     b->step += t.ts;
@@ -1471,6 +1485,31 @@ int lbm_batch_set_graph_steps(lbm_batch* b, int32_t k) {
   if (k > 0 && b->st == nullptr) return LBM_EINVAL;
   batch_drop_graphs(b);
   b->graph_k = k;
+  return batch_prepare_graphs(b);
+}
+
+int lbm_batch_set_mrt(lbm_batch* b, const double* rates) {
+  if (!b) return LBM_EINVAL;
+  if (rates) {
+    if (b->prec != LBM_PREC_F64 && b->prec != LBM_PREC_F32DEV) return LBM_ENOTSUP;
+    for (int r = 0; r < b->nruns; ++r) {
+      if (b->p[r].scheme != LBM_SCHEME_IMPROVED) return LBM_ENOTSUP;
+      for (int i = 0; i < 3; ++i)
+        if (!(rates[3 * r + i] > 0.0 && rates[3 * r + i] < 2.0)) return LBM_EINVAL;
+    }
+  }
+  for (int r = 0; r < b->nruns; ++r) {
+    RunDev& d = b->d[r];
+    // back to the BGK values make_rundev sets, then the run's MRT rates
+    d.mrt = 0;
+    d.s_e = d.s_eps = d.s_q = d.inv_tau;
+    d.sig_e = d.sig_eps = d.sig;
+    if (rates) set_mrt(d, b->p[r], rates + 3 * r);
+  }
+  HIPCHK(hipMemcpyAsync(b->d_runs, b->d.data(), b->nruns * sizeof(RunDev), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  b->mrt = rates ? 1 : 0;
+  batch_drop_graphs(b);  // the captured launches are of the other kernels
   return batch_prepare_graphs(b);
 }
 
@@ -1508,7 +1547,7 @@ int lbm_batch_tune(lbm_batch* b, int32_t* nw_out, int32_t* L_out, int32_t* depth
         const float ms = time_launches(
             b->st,
             [&] {
-              return launch_batch(b->prec, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items,
+              return launch_batch(b->prec, b->mrt != 0, t, b->buf[s], b->buf[s ^ 1], b->d_runs, b->d_items,
                                   b->nitems, b->total_rows, nullptr, (unsigned long long)b->step,
                                   b->flags, b->st);
             },

@@ -85,6 +85,7 @@ _SIGS = {
     "lbm_batch_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "lbm_batch_get_tile": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     "lbm_batch_set_graph_steps": (C.c_int, [_vp, C.c_int32]),
+    "lbm_batch_set_mrt": (C.c_int, [_vp, _vp]),
     "lbm_batch_graph_captures": (C.c_int, [_vp, _lp]),
     "lbm_batch_nodes": (C.c_int, [_vp, _lp]),
     "lbm_batch_destroy": (C.c_int, [_vp]),
@@ -397,6 +398,18 @@ class Batch:
 
     def set_graph_steps(self, k: int):
         _check(lib().lbm_batch_set_graph_steps(self.b, int(k)), "lbm_batch_set_graph_steps")
+
+    def set_mrt(self, rates=None):
+        """MRT collision for every run: rates = (s_e, s_eps, s_q) for all runs, or
+        one such triple per run; None restores BGK."""
+        if rates is None:
+            _check(lib().lbm_batch_set_mrt(self.b, None), "lbm_batch_set_mrt")
+            return
+        r = np.asarray(rates, dtype=np.float64)
+        if r.ndim == 1:
+            r = np.tile(r, (len(self.ps), 1))
+        r = np.ascontiguousarray(r.reshape(len(self.ps), 3))
+        _check(lib().lbm_batch_set_mrt(self.b, r.ctypes.data), "lbm_batch_set_mrt")
 
     def graph_captures(self) -> int:
         n = C.c_int64()

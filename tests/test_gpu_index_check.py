@@ -76,6 +76,14 @@ def test_batch_frozen_mrt_and_diagnostics_in_bounds(CL):
         for i in range(len(gps)):
             b.moments(i, check=False)
         b.close()
+    mrt_gps = [g for g in gps if g.scheme == 2]
+    mrt_rhos = [r for g, r in zip(gps, rhos) if g.scheme == 2]
+    for tile in [(1, 4, 2), (4, 0, 2), (4, 0, 2, 2), (2, 8, 1, 2)]:
+        b = L.Batch(mrt_gps, mrt_rhos)
+        b.set_mrt((1.3, 1.1, 1.2))
+        b.set_tile(*tile)
+        b.step(9)
+        b.close()
     gp, _ = pair(L, 130, 70, t=0.85, tau=0.9, scheme=2, sigma=0.105)
     lat = L.Lattice(gp, slab_rho(130, 70, CS, 0.85))
     lat.set_mrt((1.3, 1.1, 1.2))

@@ -152,3 +152,76 @@ def test_mrt_arguments(L):
     lat.set_mrt(None)                              # back to BGK: three steps allowed again
     lat.set_tile(4, 0, 1, 3)
     lat.close()
+
+
+BATCH_RUNS = [(96, 32, 0.8, 0.8, 0.10, (1.3, 1.1, 1.2)), (200, 48, 0.7, 1.1, 0.05, (1.6, 0.8, 1.9)),
+              (64, 16, 0.9, 0.6, 0.15, (1.0, 1.5, 1.1)), (130, 40, 0.75, 1.4, 0.0, (1.2, 1.2, 1.2)),
+              (513, 17, 0.8, 0.9, 0.2, (1.7, 0.6, 1.4))]
+
+
+def _batch_runs(L, prec):
+    gps, rhos, rates = [], [], []
+    for i, (nx, ny, t, tau, sigma, r) in enumerate(BATCH_RUNS):
+        gp, _ = pair(L, nx, ny, t=t, tau=tau, scheme=2, sigma=sigma, precision=prec)
+        gps.append(gp)
+        rhos.append(slab_rho(nx, ny, CS, t, seed=40 + i))
+        rates.append(r)
+    return gps, rhos, rates
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mrt_batch_equals_single_lattices_bitwise(L, prec):
+    # per-run rates through lbm_batch_set_mrt: every run of every batch tile (one
+    # and two steps per launch, graphs with a remainder) equals a single lattice
+    # with the same rates
+    gps, rhos, rates = _batch_runs(L, prec)
+    ref = []
+    for gp, rho, r in zip(gps, rhos, rates):
+        lat = L.Lattice(gp, rho)
+        lat.set_mrt(r)
+        lat.step(37)
+        ref.append(lat.get_populations()[0].tobytes())
+        lat.close()
+    for tile, graph in [((1, 4, 1, 1), 0), ((2, 0, 2, 1), 0), ((2, 0, 2, 2), 0), ((4, 32, 1, 2), 0),
+                        ((2, 0, 1, 2), 10)]:
+        b = L.Batch(gps, rhos)
+        b.set_mrt(rates)
+        b.set_tile(*tile)
+        if graph:
+            b.set_graph_steps(graph)
+        b.step(3)
+        b.step(34)
+        got = [b.get_populations(i).tobytes() for i in range(len(gps))]
+        b.close()
+        assert got == ref, (prec, tile)
+
+
+def test_mrt_batch_arguments_and_reset(L):
+    gps, rhos, rates = _batch_runs(L, 0)
+    bgk = L.Batch(gps, rhos)
+    bgk.step(20)
+    want = [bgk.get_populations(i).tobytes() for i in range(len(gps))]
+    bgk.close()
+    b = L.Batch(gps, rhos)
+    for bad in [(0.0, 1.0, 1.0), (1.0, 2.0, 1.0), (1.0, 1.0, float("nan"))]:
+        with pytest.raises(L.LbmError) as e:
+            b.set_mrt(bad)
+        assert e.value.status == L.LBM_EINVAL
+    b.set_mrt(rates)
+    b.set_tile(2, 0, 2, 2)
+    b.set_mrt(None)                                  # back to BGK before any step
+    b.step(20)
+    assert [b.get_populations(i).tobytes() for i in range(len(gps))] == want
+    b.close()
+    gp_sc, _ = pair(L, 64, 32, t=0.8, tau=0.8, scheme=0)
+    b = L.Batch(gps[:2] + [gp_sc], rhos[:2] + [slab_rho(64, 32, CS, 0.8)])
+    with pytest.raises(L.LbmError) as e:
+        b.set_mrt(RATES)                             # one Shan-Chen run: improved scheme only
+    assert e.value.status == L.LBM_ENOTSUP
+    b.close()
+    gps16, rhos16, _ = _batch_runs(L, 2)
+    b = L.Batch(gps16, rhos16)
+    with pytest.raises(L.LbmError) as e:
+        b.set_mrt(RATES)                             # FP16 storage
+    assert e.value.status == L.LBM_ENOTSUP
+    b.close()
