@@ -248,9 +248,9 @@ int lbm_set_graph_steps(lbm_ctx* c, int32_t k);
  * c_s^2 (1/s_e - 1/2).  Each moment gets Eq. (31)'s forcing moment with
  * v' = v + sigma F / ((1/s - 1/2) psi^2) for its own rate s, so rates all equal
  * to 1/tau give the BGK improved scheme.  Improved scheme only, FP64 or FP32
- * deviation storage (else LBM_ENOTSUP); one- and two-step tiles (a three-step
- * tile becomes the same tile with one step; lbm_set_tile with steps = 3 then
- * returns LBM_ENOTSUP).  Captured graphs are rebuilt. */
+ * deviation storage (else LBM_ENOTSUP); every tile of the lattice's precision
+ * (one, two and, for FP64, three steps per launch), bitwise equal to one
+ * another.  Captured graphs are rebuilt. */
 int lbm_set_mrt(lbm_ctx* c, const double* rates);
 
 /* Number of graphs captured over the context's life (a tool can check that a

@@ -985,7 +985,7 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const typename Store<S>::E* _
 // rows from the lane's own registers and the six shifted ones through an LDS
 // exchange row, as in tile_step2; two barriers per march row.  Same
 // arithmetic in the same order as three single-step launches: bitwise equal.
-template <typename S, int NW>
+template <typename S, int NW, bool MRT = false>
 __device__ __forceinline__ void tile_step3(const typename Store<S>::E* __restrict__ src,
                                            typename Store<S>::E* __restrict__ dst,
                                            const RunDev& d, int x0, int y0, int ncols, int nrows,
@@ -1116,7 +1116,7 @@ __device__ __forceinline__ void tile_step3(const typename Store<S>::E* __restric
         const bool chk = out && y1 >= y0 && y1 < y0 + nrows;
         bad1 |= chk && (!(psi2c > P(0)) || !(rho > P(0)));
         const R ip2 = d.sig != 0.0 ? rcp(R(psi2c)) : R(0);
-        update_node<S, false>(fc, drho, rho, Fx, Fy, ip2, d);
+        update_node<S, MRT>(fc, drho, rho, Fx, Fy, ip2, d);
 #pragma unroll
         for (int a = 0; a < 9; ++a) gA[a] = T::round(fc[a]);
       }
@@ -1141,7 +1141,7 @@ __device__ __forceinline__ void tile_step3(const typename Store<S>::E* __restric
         const bool chk = out && r2 >= y0 && r2 < y0 + nrows;
         bad2 |= chk && (!(psi2p > P(0)) || !(rho > P(0)));
         const R ip2 = d.sig != 0.0 ? rcp(R(psi2p)) : R(0);
-        update_node<S, false>(hp, drho, rho, Fx, Fy, ip2, d);
+        update_node<S, MRT>(hp, drho, rho, Fx, Fy, ip2, d);
 #pragma unroll
         for (int a = 0; a < 9; ++a) kA[a] = T::round(hp[a]);
       }
@@ -1159,7 +1159,7 @@ __device__ __forceinline__ void tile_step3(const typename Store<S>::E* __restric
       const P rho = rref + P(drho);
       bad3 |= !(psi3p > P(0)) || !(rho > P(0));
       const R ip2 = d.sig != 0.0 ? rcp(R(psi3p)) : R(0);
-      update_node<S, false>(hp3, drho, rho, Fx, Fy, ip2, d);
+      update_node<S, MRT>(hp3, drho, rho, Fx, Fy, ip2, d);
       typename T::E* orow = dst + (int64_t)wrapy(r3) * d.rs;
 #pragma unroll
       for (int a = 0; a < 9; ++a)
@@ -1187,7 +1187,7 @@ __device__ __forceinline__ void tile_step3(const typename Store<S>::E* __restric
 // strips of at most 64*NW - 10 columns spread evenly over nx, edges aligned as
 // for the two-step kernel; L > 0: one block per (strip, L-row chunk); L == 0:
 // the balanced schedule of k_step2.
-template <typename S, int NW>
+template <typename S, int NW, bool MRT = false>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_step3(const typename Store<S>::E* __restrict__ src,
                                                    typename Store<S>::E* __restrict__ dst,
                                                    RunDev d, int L, int nstrips,
@@ -1220,7 +1220,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     if (frozen)
       copy_tile<S, 64 * NW>(src, dst, d, x0, y0, nc, min(L, d.ny - y0));
     else
-      tile_step3<S, NW>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2, ring3,
+      tile_step3<S, NW, MRT>(src, dst, d, x0, y0, nc, min(L, d.ny - y0), step, flag, ring1, ring2, ring3,
                         xch1, xch2);
     return;
   }
@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     if (frozen)
       copy_tile<S, 64 * NW>(src, dst, d, x0, y, nc, n);
     else
-      tile_step3<S, NW>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, ring3, xch1, xch2);
+      tile_step3<S, NW, MRT>(src, dst, d, x0, y, nc, n, step, flag, ring1, ring2, ring3, xch1, xch2);
     r += n;
     __syncthreads();  // LDS is reused by the next piece
   }

@@ -289,7 +289,7 @@ hipError_t launch_step2_s(const Tile& t, const void* src, void* dst, const RunDe
   }
 }
 
-template <typename S, int NW>
+template <typename S, int NW, bool MRT = false>
 hipError_t launch_step3_t(const void* src, void* dst, const RunDev& d, int L,
                           const unsigned long long* base, unsigned long long local,
                           unsigned long long* flag, hipStream_t st) {
@@ -302,11 +302,11 @@ hipError_t launch_step3_t(const void* src, void* dst, const RunDev& d, int L,
     grid = nstrips * ((d.ny + L - 1) / L);
   } else {
     const int64_t rows = (int64_t)nstrips * d.ny;
-    grid = resident_blocks((const void*)k_step3<S, NW>, SW);
+    grid = resident_blocks((const void*)k_step3<S, NW, MRT>, SW);
     grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, rows / 8));
   }
   using E = typename Store<S>::E;
-  hipLaunchKernelGGL((k_step3<S, NW>), dim3(grid), dim3(SW), 0, st, static_cast<const E*>(src),
+  hipLaunchKernelGGL((k_step3<S, NW, MRT>), dim3(grid), dim3(SW), 0, st, static_cast<const E*>(src),
                      static_cast<E*>(dst), d, L, nstrips, base, local, flag);
   return hipGetLastError();
 }
@@ -320,6 +320,9 @@ bool has_step3(int prec) { return prec == LBM_PREC_F64 || prec == LBM_PREC_F32DE
 hipError_t launch_step(int prec, const Tile& t, const void* src, void* dst, const RunDev& d,
                        const unsigned long long* base, unsigned long long local,
                        unsigned long long* flag, hipStream_t st) {
+  if (t.ts == 3 && d.mrt)  // FP64 only: the one precision with both MRT and three steps
+    return t.nw == 8 ? launch_step3_t<double, 8, true>(src, dst, d, t.L, base, local, flag, st)
+                     : launch_step3_t<double, 4, true>(src, dst, d, t.L, base, local, flag, st);
   if (t.ts == 3) {
     if (prec == LBM_PREC_F64)
       return t.nw == 8 ? launch_step3_t<double, 8>(src, dst, d, t.L, base, local, flag, st)
@@ -1038,7 +1041,6 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
 
 int lbm_set_tile(lbm_ctx* c, int32_t nw, int32_t L, int32_t depth, int32_t steps) {
   if (!c || !valid_tile(nw, L, depth, 16, steps)) return LBM_EINVAL;
-  if (c->d.mrt && steps == 3) return LBM_ENOTSUP;
   if (steps == 3 && !has_step3(c->p.precision)) return LBM_ENOTSUP;
   if (steps == 3 && (c->p.nx < 5 || c->p.ny < 5)) return LBM_EINVAL;  // halo of 5 wraps once
   c->tile = Tile{nw, L, depth, steps};
@@ -1074,7 +1076,7 @@ int lbm_tune(lbm_ctx* c, int32_t* nw_out, int32_t* L_out, int32_t* depth_out, in
       for (int L : {0, 32, 64, 128})
         if (L <= 2 * c->p.ny) cand.push_back(Tile{nw, L, pf, 2});
   }
-  if (!c->d.mrt && has_step3(c->p.precision) && c->p.nx >= 16 && c->p.ny >= 16)
+  if (has_step3(c->p.precision) && c->p.nx >= 16 && c->p.ny >= 16)
     for (int nw : {4, 8}) {
       if (nw > 4 && 64 * (nw / 2) >= c->p.nx) continue;
       for (int L : {0, 64, 128})
@@ -1130,7 +1132,6 @@ int lbm_set_mrt(lbm_ctx* c, const double* rates) {
     if (!(rates[i] > 0.0 && rates[i] < 2.0)) return LBM_EINVAL;
   c->d = make_rundev(c->p, c->k, c->p.rho_ref, 0, 0);
   set_mrt(c->d, c->p, rates);
-  if (c->tile.ts == 3) c->tile = Tile{c->tile.nw, c->tile.L, c->tile.pf, 1};
   drop_graphs(c);  // the captured launches carry the old constants
   return prepare_graphs(c);
 }

@@ -2,7 +2,7 @@
 load and store of the step, copy and mass kernels is checked against its
 lattice's buffer and every tile shape against the kernel's limits.  The tests
 drive edge shapes, every tile family, the batch (item lists and the balanced
-schedule), frozen runs, MRT (one- and two-step tiles) and the diagnostics, and require zero violations."""
+schedule), frozen runs, MRT (every tile family) and the diagnostics, and require zero violations."""
 import ctypes as C
 
 import numpy as np
@@ -87,7 +87,7 @@ def test_batch_frozen_mrt_and_diagnostics_in_bounds(CL):
     gp, _ = pair(L, 130, 70, t=0.85, tau=0.9, scheme=2, sigma=0.105)
     lat = L.Lattice(gp, slab_rho(130, 70, CS, 0.85))
     lat.set_mrt((1.3, 1.1, 1.2))
-    for tile in ONE + TWO:
+    for tile in ONE + TWO + THREE:
         lat.set_tile(*tile)
         lat.step(4)
     lat.flat_profile(pressure=False)    # p_n is not defined for MRT; the column means are

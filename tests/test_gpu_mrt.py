@@ -54,7 +54,7 @@ def test_mrt_slab_matches_oracle(L, rates):
     assert max(errs) < TOL64, errs
 
 
-@pytest.mark.parametrize("tile", [(2, 16, 1), (4, 16, 1, 2)])
+@pytest.mark.parametrize("tile", [(2, 16, 1), (4, 16, 1, 2), (4, 16, 1, 3)])
 def test_mrt_peng_robinson_droplet_ragged_tile(L, tile):
     gp, op = _mrt_pair(L, 130, 70, t=0.85, tau=0.9, scheme=2, sigma=0.105, eos=PR)
     errs = _run(L, gp, op, droplet_rho(130, 70, PR, 0.85, 20), [1, 50, 500], tile=tile)
@@ -98,7 +98,8 @@ def test_mrt_tiles_and_graphs_bitwise(L):
     rho0 = slab_rho(200, 90, CS, 0.8, seed=3)
     outs = []
     for tile, graph in [((1, 4, 1), 0), ((4, 0, 2), 0), ((16, 7, 1), 0), ((2, 0, 2), 10),
-                        ((4, 0, 2, 2), 0), ((8, 5, 1, 2), 0), ((4, 32, 1, 2), 10), ((8, 0, 2, 2), 12)]:
+                        ((4, 0, 2, 2), 0), ((8, 5, 1, 2), 0), ((4, 32, 1, 2), 10), ((8, 0, 2, 2), 12),
+                        ((4, 0, 1, 3), 0), ((8, 16, 1, 3), 0), ((4, 0, 1, 3), 10), ((4, 5, 1, 3), 12)]:
         lat = L.Lattice(gp, rho0)
         lat.set_mrt(RATES)
         lat.set_tile(*tile)
@@ -142,15 +143,17 @@ def test_mrt_arguments(L):
     lat.set_tile(4, 0, 2, 2)
     lat.set_mrt(RATES)
     assert lat.get_tile() == (4, 0, 2, 2)          # the two-step kernel carries MRT
+    lat.set_tile(4, 0, 1, 3)                       # and the FP64 three-step kernel
+    lat.set_mrt((1.2, 1.2, 1.2))
+    assert lat.get_tile() == (4, 0, 1, 3)
     lat.set_mrt(None)
-    lat.set_tile(4, 0, 1, 3)
-    lat.set_mrt(RATES)                             # a three-step tile becomes one step
-    assert lat.get_tile() == (4, 0, 1, 1)
+    lat.close()
+    gp, _ = pair(L, 64, 32, t=0.8, tau=0.8, scheme=2, sigma=0.1, precision=1)
+    lat = L.Lattice(gp, rho0)
+    lat.set_mrt(RATES)
     with pytest.raises(L.LbmError) as e:
-        lat.set_tile(4, 0, 1, 3)
+        lat.set_tile(4, 0, 1, 3)                   # FP32 arithmetic: no three-step kernel
     assert e.value.status == L.LBM_ENOTSUP
-    lat.set_mrt(None)                              # back to BGK: three steps allowed again
-    lat.set_tile(4, 0, 1, 3)
     lat.close()
 
 

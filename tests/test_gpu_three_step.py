@@ -154,11 +154,11 @@ def test_three_step_rejected_where_unsupported(L):
     for tile in [(16, 0, 1, 3), (4, 0, 2, 3), (2, 0, 1, 3)]:
         with pytest.raises(L.LbmError):
             lat.set_tile(*tile)
-    # the three-step kernel has no MRT collision: a three-step tile is refused, and
-    # switching to MRT turns a three-step tile into the one-step tile of the same shape
+    # the FP64 three-step kernel carries the MRT collision: switching to MRT keeps a
+    # three-step tile, and three-step tiles are accepted under MRT
     lat.set_tile(4, 0, 1, 3)
     lat.set_mrt((1.3, 1.1, 1.2))
-    assert lat.get_tile() == (4, 0, 1, 1)
-    with pytest.raises(L.LbmError):
-        lat.set_tile(4, 0, 1, 3)
+    assert lat.get_tile() == (4, 0, 1, 3)
+    lat.set_tile(8, 0, 1, 3)
+    assert lat.get_tile() == (8, 0, 1, 3)
     lat.close()
