@@ -279,6 +279,28 @@ def test_full_size_droplets4096_sampled(L, prec, tol):
     lat.close()
 
 
+def test_full_size_benchmarked_fp64_tiles_bitwise(L):
+    # the FP64 launch shapes the benchmark times on 4096 x 4096 (one step 16x0x1, two
+    # steps 4x0x2, three steps 4x0x1, whose output the sampled oracle test above
+    # checks) give the same bits after 12 steps from the same state
+    gp, _ = pair(L, 4096, 4096, t=0.7, tau=0.8, scheme=2, sigma=0.1)
+    c = th.maxwell_cs(0.7)
+    centers, radii = synth.droplet_layout(4096, 4096, 64, 40.0, 120.0, 16.0, synth.BASE_SEED)
+    rho0 = synth.droplets(4096, 4096, c.rho_l, c.rho_g, centers, radii, 2.0, 0.005, synth.BASE_SEED)
+    first = None
+    for tile in [(4, 0, 1, 3), (16, 0, 1, 1), (4, 0, 2, 2)]:
+        lat = L.Lattice(gp, rho0)
+        lat.set_tile(*tile)
+        lat.set_graph_steps(6)
+        lat.step(12)
+        state = lat.save_state()
+        lat.close()
+        if first is None:
+            first = state
+        else:
+            assert state == first, tile
+
+
 @pytest.mark.parametrize("steps", [0, 300])
 def test_batch_coexistence_kernel_vs_oracle(L, steps):
     # the device reduction of rho_l / rho_g against the oracle's column means of
