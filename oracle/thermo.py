@@ -1,7 +1,7 @@
 """Thermodynamic analysis oracle (TEST INFRASTRUCTURE ONLY).
 
 High-precision (mpmath) solvers for the coexistence densities the
-pseudopotential lattice Boltzmann model is judged against:
+pseudopotential lattice Boltzmann model is compared with:
 
   * equations of state: Carnahan-Starling (paper Sec. III.C, Eq. 23) and
     Peng-Robinson (not in the paper; standard form with

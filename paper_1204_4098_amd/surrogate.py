@@ -159,7 +159,7 @@ def slope_log_rho_g(net, t_over_tc, tau, sigma, h=2e-3):
 
 
 def propose_and_verify(net, pairs, steps=30000, tol=0.01, bisect_iters=8, nx=256, ny=32):
-    """The learned proposal with the lattice as judge.  Returns per pair the sigma
+    """The learned proposal, each pick checked by a lattice run.  Returns per pair the sigma
     used, its relative errors against Maxwell (rho_l, rho_g) and how many FP64
     lattice runs it took."""
     sig = np.array([propose_sigma(net, t, tau)[0] for t, tau in pairs])

@@ -438,7 +438,7 @@ def test_divergence_and_invalid_input():
 
 def test_laplace_law_droplets():
     # Laplace's law: the pressure jump across a droplet interface is linear in 1/R
-    # with no offset (paper silent; spec validation of the oracle)
+    # with no offset (the paper does not test it; a physical check of the oracle)
     Tc, _ = th.critical_cs()
     c = th.maxwell_cs(0.8)
     N = 64
