@@ -1376,42 +1376,47 @@ __global__ void k_counter_set(unsigned long long* ctr, unsigned long long v) { *
 // ---- diagnostics (rare; simple one-node-per-thread kernels) ---------------
 
 // Pass 1: rho, u = j/rho and psi at every node (rho/ux/uy/psi planes, [y][x]).
+// Rows blockIdx.y, blockIdx.y + gridDim.y, ... (the grid's y extent is capped).
 template <typename S>
 __global__ void k_moments1(const typename Store<S>::E* __restrict__ src, RunDev d, double* rho, double* ux,
                            double* uy, double* psi) {
   using R = typename Store<S>::R;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= d.nx) return;
-  R f[9];
-  pull9<S>(src, d, cols_of(x, d.nx), y, f);
-  const R drho = sum9(f);
-  const double r = d.rho_ref + double(drho);
-  const int64_t o = (int64_t)y * d.nx + x;
-  rho[o] = r;
-  ux[o] = double(mom_x(f) / R(r));
-  uy[o] = double(mom_y(f) / R(r));
-  psi[o] = sqrt(psi2_of(r, d));
+  for (int y = blockIdx.y; y < d.ny; y += gridDim.y) {
+    R f[9];
+    pull9<S>(src, d, cols_of(x, d.nx), y, f);
+    const R drho = sum9(f);
+    const double r = d.rho_ref + double(drho);
+    const int64_t o = (int64_t)y * d.nx + x;
+    rho[o] = r;
+    ux[o] = double(mom_x(f) / R(r));
+    uy[o] = double(mom_y(f) / R(r));
+    psi[o] = sqrt(psi2_of(r, d));
+  }
 }
 
 // Pass 2: v = u + F/(2 rho) (Table I, actual velocity) and p = p_EOS(rho).
 __global__ void k_moments2(RunDev d, const double* __restrict__ psi, const double* rho, double* vx,
                            double* vy, double* p) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= d.nx) return;
   const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
-  const double* rs = psi + (int64_t)ym * d.nx;
-  const double* rc = psi + (int64_t)y * d.nx;
-  const double* rn = psi + (int64_t)yp * d.nx;
-  const double s[3] = {rs[xm], rs[x], rs[xp]}, c[3] = {rc[xm], rc[x], rc[xp]},
-               n[3] = {rn[xm], rn[x], rn[xp]};
-  double Fx, Fy;
-  force3x3(s, c, n, 1, d.mG, Fx, Fy);
-  const int64_t o = (int64_t)y * d.nx + x;
-  const double r = rho[o];
-  vx[o] += Fx / (2.0 * r);
-  vy[o] += Fy / (2.0 * r);
-  p[o] = pressure_of(r, d);
+  for (int y = blockIdx.y; y < d.ny; y += gridDim.y) {
+    const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+    const double* rs = psi + (int64_t)ym * d.nx;
+    const double* rc = psi + (int64_t)y * d.nx;
+    const double* rn = psi + (int64_t)yp * d.nx;
+    const double s[3] = {rs[xm], rs[x], rs[xp]}, c[3] = {rc[xm], rc[x], rc[xp]},
+                 n[3] = {rn[xm], rn[x], rn[xp]};
+    double Fx, Fy;
+    force3x3(s, c, n, 1, d.mG, Fx, Fy);
+    const int64_t o = (int64_t)y * d.nx + x;
+    const double r = rho[o];
+    vx[o] += Fx / (2.0 * r);
+    vy[o] += Fy / (2.0 * r);
+    p[o] = pressure_of(r, d);
+  }
 }
 
 // Flat interface with normal x: mean density of each column (fixed order in y).

@@ -455,7 +455,8 @@ hipError_t launch_batch(int prec, bool mrt, const Tile& t, const void* src, void
 template <typename S>
 hipError_t launch_moments_s(const void* src, const RunDev& d, double* rho, double* vx, double* vy,
                             double* p, double* psi, hipStream_t st) {
-  dim3 blk(64), grd((d.nx + 63) / 64, d.ny);
+  // rows beyond the grid's y extent (at most 65535 here) are looped in the kernels
+  dim3 blk(64), grd((d.nx + 63) / 64, std::min(d.ny, 65535));
   hipLaunchKernelGGL(k_moments1<S>, grd, blk, 0, st, static_cast<const typename Store<S>::E*>(src), d, rho,
                      vx, vy, psi);
   hipLaunchKernelGGL(k_moments2, grd, blk, 0, st, d, (const double*)psi, (const double*)rho, vx, vy, p);

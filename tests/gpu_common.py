@@ -41,3 +41,18 @@ def droplet_rho(nx, ny, eos, t, r0, noise=0.005, seed=synth.BASE_SEED):
 
 def rel_err(a, b):
     return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+MIRROR_X = [0, 3, 2, 1, 4, 6, 5, 8, 7]   # direction index after x -> -x
+MIRROR_Y = [0, 1, 4, 3, 2, 8, 7, 6, 5]   # direction index after y -> -y
+
+
+def mirror_tile(win):
+    """A 2w x 2w periodic lattice made of the window and its three mirror images,
+    so that wrapping creates no density jump."""
+    mx = win[MIRROR_X][:, :, ::-1]
+    my = win[MIRROR_Y][:, ::-1, :]
+    mxy = win[MIRROR_X][MIRROR_Y][:, ::-1, ::-1]
+    top = np.concatenate([win, mx], axis=2)
+    bot = np.concatenate([my, mxy], axis=2)
+    return np.ascontiguousarray(np.concatenate([top, bot], axis=1))

@@ -6,7 +6,7 @@ import pytest
 import synth
 from oracle import lbm as olbm
 from oracle import thermo as th
-from tests.gpu_common import CS, PR, pair, rel_err, slab_rho, droplet_rho
+from tests.gpu_common import CS, PR, pair, rel_err, slab_rho, droplet_rho, mirror_tile
 
 pytestmark = pytest.mark.gpu
 
@@ -214,21 +214,6 @@ def test_batch_graph_bitwise(L, tile, k):
     a.close(); b.close()
 
 
-MIRROR_X = [0, 3, 2, 1, 4, 6, 5, 8, 7]   # direction index after x -> -x
-MIRROR_Y = [0, 1, 4, 3, 2, 8, 7, 6, 5]   # direction index after y -> -y
-
-
-def _mirror_tile(win):
-    """A 2w x 2w periodic lattice made of the window and its three mirror images,
-    so that wrapping creates no density jump."""
-    mx = win[MIRROR_X][:, :, ::-1]
-    my = win[MIRROR_Y][:, ::-1, :]
-    mxy = win[MIRROR_X][MIRROR_Y][:, ::-1, ::-1]
-    top = np.concatenate([win, mx], axis=2)
-    bot = np.concatenate([my, mxy], axis=2)
-    return np.ascontiguousarray(np.concatenate([top, bot], axis=1))
-
-
 def _window_check(L, lat, op, nx, ny, points, k=4, half=20):
     """Full-size sampled parity: the state after k more steps near each point
     is reproduced by the oracle run on a window around it (the light cone of k
@@ -240,7 +225,7 @@ def _window_check(L, lat, op, nx, ny, points, k=4, half=20):
     for (cx, cy) in points:
         ys = (np.arange(cy - half, cy + half) % ny)
         xs = (np.arange(cx - half, cx + half) % nx)
-        win = _mirror_tile(f_now[:, ys][:, :, xs])
+        win = mirror_tile(f_now[:, ys][:, :, xs])
         wp = olbm.Params(**{**op.__dict__, "nx": 2 * w, "ny": 2 * w})
         assert olbm.step(wp, win, k)[0] == 0
         m = 2 * k + 1
