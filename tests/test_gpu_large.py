@@ -1,8 +1,10 @@
-"""A lattice beyond 2^31 population elements and taller than a grid's 65535-row
-extent: 4096 x 70000 FP64 (2.58e9 elements, 20.6 GB per buffer).  Windows around
-nodes near the first and the last rows, where the element offsets pass 2^31, are
-stepped by the oracle from the same initial state and compared with the device
-densities after each tile family (three, two and one steps per launch)."""
+"""Sizes past 32-bit element offsets.  A lattice beyond 2^31 population elements
+and taller than a grid's 65535-row extent: 4096 x 70000 FP64 (2.58e9 elements,
+20.6 GB per buffer); windows around nodes near the first and the last rows, where
+the element offsets pass 2^31, are stepped by the oracle from the same initial
+state and compared with the device densities after each tile family (three, two
+and one steps per launch).  A batch whose last run starts past element 2^31 of
+its pool, against a single lattice."""
 import numpy as np
 import pytest
 
@@ -55,3 +57,24 @@ def test_lattice_beyond_2_31_elements(L):
             assert err < 1e-12, (tile, (cx, cy), err)
         del rho
     lat.close()
+
+
+def test_batch_run_past_2_31_elements(L):
+    # two 4096 x 30000 FP64 runs (1.1e9 elements each) put the third run's
+    # populations past element 2^31 of the pool; that run, stepped by the batched
+    # one- and two-step kernels, equals a single lattice bit for bit
+    big, _ = pair(L, 4096, 30000, t=0.8, tau=0.9, scheme=2, sigma=0.1)
+    small, _ = pair(L, 96, 32, t=0.8, tau=0.8, scheme=2, sigma=0.1)
+    rb = slab_rho(4096, 30000, CS, 0.8, seed=61)
+    rs = slab_rho(96, 32, CS, 0.8, seed=62)
+    assert 2 * 9 * 4096 * 30000 > 2 ** 31
+    lat = L.Lattice(small, rs)
+    lat.step(7)
+    want = lat.get_populations()[0].tobytes()
+    lat.close()
+    for tile in [(2, 0, 2, 2), (4, 8, 2, 1)]:
+        b = L.Batch([big, big, small], [rb, rb, rs])
+        b.set_tile(*tile)
+        b.step(7)
+        assert b.get_populations(2).tobytes() == want, tile
+        b.close()
